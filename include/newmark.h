@@ -1,0 +1,152 @@
+/*
+ * newmark.h -- C ABI of the MI355X (gfx950) implicit FFT Newmark solver.
+ *
+ * Implements the hot path of Sancho, Rey de Pedraza, Lafourcade, Lebensohn
+ * and Segurado, "An implicit FFT-based method for wave propagation in elastic
+ * heterogeneous media" (arXiv 2211.08263): each Newmark-beta step (eq. Newmark,
+ * beta = 1/4, gamma = 1/2) solves the discretized momentum balance of eq.
+ * (ND_consv_lm_Newmark_ord) with the matrix-free operator of eq.
+ * (Fourier_ND_A), preconditioned conjugate gradients (section 2.2.3) and the
+ * reference-medium preconditioner of eqs. (precond)-(acous), while the
+ * displacement is prescribed on the voxel set Gamma (eqs. (f), (new)).
+ *
+ * Conventions
+ *  - Grid n1 x n2 x n3 voxels, x fastest; voxel (i,j,k) has linear index
+ *    i + n1*(j + n2*k) and centre ((i+1/2) L1/n1, ...) (section 2.2.3).
+ *  - Vector fields are SoA: component c of voxel v at c*N + v, N = n1 n2 n3.
+ *    Device fields always hold 3 components; for dim == 2 (plane strain,
+ *    n3 == 1) the third component is kept at zero.
+ *  - Stiffness: per phase, the 21 upper-triangle entries (row major) of the
+ *    6x6 Voigt matrix in the order 11,22,33,23,13,12 with engineering shear
+ *    strains.  Density: one value per phase.
+ *  - Discrete frequencies in standard DFT order with the Nyquist bin set to
+ *    zero (the paper uses odd grids only; this keeps the operator real,
+ *    symmetric and positive definite on even grids).
+ *  - Every function returns NM_OK (0) or a negative NM_E* code; the message is
+ *    available from nm_last_error().  No exception crosses the ABI.
+ *  - One context per host thread.  All device work runs on the context's HIP
+ *    stream.
+ */
+#ifndef NEWMARK_H
+#define NEWMARK_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+enum nm_status {
+    NM_OK = 0,
+    NM_EINVAL = -1,       /* bad argument: shapes, dtypes, Gamma index range, null pointers */
+    NM_EUNSUPPORTED = -2, /* dim not 2/3, or an axis not a power of two in [8, 512] (n3 == 1 in 2D) */
+    NM_ENOMEM = -3,       /* device or pinned-host allocation failed */
+    NM_ENOTCONV = -4,     /* Krylov solve hit max_iter; the state is left at the previous step */
+    NM_ESINGULAR = -5,    /* zero pivot in the Green-matrix factorization */
+    NM_ENAN = -6,         /* non-finite value in the prescribed displacement or a residual */
+    NM_EHIP = -7          /* HIP runtime error */
+};
+
+enum nm_dtype { NM_FP64 = 0, NM_FP32 = 1 };
+enum nm_precision { NM_PREC_FP64 = 0, NM_PREC_MIXED = 1 };
+enum nm_route { NM_ROUTE_AUTO = 0, NM_ROUTE_GREEN = 1, NM_ROUTE_PROJECTED = 2 };
+enum nm_warm_start { NM_WS_COLD = 0, NM_WS_PREV = 1, NM_WS_TAYLOR = 2, NM_WS_LEARNED = 3 };
+
+/* Inputs of the paper's Algorithm 2 (KwData): microstructure, Gamma, initial
+ * state, time increment and Newmark constants.  Host arrays are copied by
+ * nm_newmark_init; the caller keeps ownership. */
+typedef struct nm_problem {
+    int dim;                  /* 2 (plane strain, n[2] == 1) or 3 */
+    int n[3];                 /* voxels per axis */
+    double L[3];              /* box lengths (L[2] ignored in 2D) */
+    int n_phases;             /* >= 1, <= 65536 */
+    const uint16_t* phase_id; /* host, N entries, each < n_phases */
+    const double* C_voigt;    /* host, n_phases x 21 */
+    const double* rho;        /* host, n_phases, > 0 */
+    const int64_t* gamma_idx; /* host, n_gamma sorted unique voxel indices in [0, N) (may be NULL if n_gamma == 0) */
+    int64_t n_gamma;
+    const double* u0;         /* host, dim x N initial displacement, or NULL for zero */
+    const double* v0;         /* host, dim x N initial velocity, or NULL for zero */
+    double dt;                /* time increment */
+    double beta;              /* Newmark beta (0.25) */
+    double gamma_nm;          /* Newmark gamma (0.5) */
+} nm_problem;
+
+typedef struct nm_options {
+    int precision;            /* nm_precision */
+    int route;                /* nm_route: GREEN (paper, G matrix + LU) or PROJECTED (PCG on the free dofs) */
+    double tol;               /* relative residual tolerance of each solve */
+    int max_iter;             /* per solve (per inner solve in mixed precision) */
+    double inner_tol;         /* mixed precision: relative tolerance of each FP32 inner solve */
+    int max_sweeps;           /* mixed precision: maximum refinement sweeps per step */
+    int warm_start;           /* nm_warm_start */
+    double green_tol;         /* tolerance of the unit-force solves that build G */
+    int compute_reaction;     /* projected route: also compute F on Gamma (one extra operator apply) */
+    int true_residual;        /* FP64 route: report ||P(b - A u)|| / ||b_ref|| (one extra operator apply) */
+} nm_options;
+
+typedef struct nm_step_stats {
+    int iters[2];             /* FP64 solves: PCG iterations (Green route: u_b, u_f; projected: [0], [1] = 0) */
+    int sweeps;               /* mixed precision: FP64 refinement sweeps */
+    int inner_iters;          /* mixed precision: total FP32 PCG iterations */
+    double relres;            /* final relative residual (true residual when measured, else recursive) */
+    double t_step_ms;         /* wall time of the step (host clock, after a stream synchronize) */
+    double t_warm_ms;         /* wall time of the warm-start prediction */
+} nm_step_stats;
+
+typedef struct nm_ctx nm_ctx;
+
+/* Build the solver: copies the problem to the device, forms the reference
+ * medium (volume averages of C and rho, eq. (precond)), the FFT twiddle
+ * tables, the Gamma route (GREEN: d*n_gamma unit-force solves of eq.
+ * (solve_green), the matrix G of eq. (G) and its LU factors) and the initial
+ * acceleration a0 = div(C : grad^s u0) / rho.  hip_stream may be NULL (a
+ * stream is created).  On success *out owns all resources. */
+int nm_newmark_init(const nm_problem* pb, const nm_options* op, void* hip_stream, nm_ctx** out);
+
+/* Advance one step: t_n = t_{n-1} + dt.  U_n (host) holds the prescribed
+ * displacement, dim values (uniform on Gamma) when per_point == 0, or
+ * dim*n_gamma values (point major) otherwise.  Returns after the stream has
+ * synchronized.  On error the state stays at step n-1.  st may be NULL. */
+int nm_newmark_step(nm_ctx* ctx, const double* U_n, int per_point, nm_step_stats* st);
+
+/* Au = A(u), eq. (Fourier_ND_A) mapped to real space, unscaled, no Gamma
+ * projection.  u_dev / Au_dev: caller-owned device buffers of 3 x N values of
+ * the given dtype (NM_FP64 or NM_FP32), SoA, distinct.  Asynchronous on the
+ * context stream. */
+int nm_apply_operator(nm_ctx* ctx, const void* u_dev, void* Au_dev, int dtype);
+
+/* z = M r with the reference-medium preconditioner of eqs. (precond)-(acous)
+ * (no Gamma projection).  Same buffer conventions as nm_apply_operator. */
+int nm_precond_apply(nm_ctx* ctx, const void* r_dev, void* z_dev, int dtype);
+
+/* FP64 PCG solve of A x = b on device buffers (3 x N doubles each).  x holds
+ * the initial guess and receives the solution.  masked != 0 runs on the free
+ * dofs only (Gamma entries of x kept, Gamma rows of b ignored), with the
+ * reference norm ||P(b - A xbar)||, xbar = x on Gamma and 0 elsewhere.
+ * Stops at ||r|| <= tol * ||b_ref||; fixed_iters >= 0 runs exactly that many
+ * iterations instead.  Synchronous.  iters / relres may be NULL. */
+int nm_pcg_solve(nm_ctx* ctx, const void* b_dev, void* x_dev, int masked, double tol, int max_iter, int fixed_iters,
+                 int* iters, double* relres);
+
+/* Checkpoint: host copies of u, v, a (dim x N each, any may be NULL), the last
+ * Gamma force F (dim*n_gamma, may be NULL) and the step count. */
+int nm_get_state(const nm_ctx* ctx, double* u, double* v, double* a, double* F_gamma, int64_t* step);
+/* Restore a checkpoint taken by nm_get_state (u, v, a required). */
+int nm_set_state(nm_ctx* ctx, const double* u, const double* v, const double* a, int64_t step);
+/* Zero-copy device views of the state (3 x N doubles each). */
+int nm_state_device_ptrs(nm_ctx* ctx, void** u, void** v, void** a);
+/* The Green matrix (d*n_gamma)^2, row major, before factorization; GREEN route only. */
+int nm_green_matrix(const nm_ctx* ctx, double* G);
+
+/* The HIP stream (hipStream_t) all of the context's work is queued on. */
+void* nm_get_stream(nm_ctx* ctx);
+
+const char* nm_last_error(const nm_ctx* ctx);
+void nm_destroy(nm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* NEWMARK_H */

@@ -1,0 +1,845 @@
+// C ABI and solver orchestration: Newmark time stepping (eq. Newmark,
+// Algorithm 2), preconditioned conjugate gradients on the FFT operator
+// (section 2.2.3), the Gamma constraint by the Green-matrix route (eqs.
+// (f_discrete)-(L-determination_ND)) or by projection onto the free dofs,
+// and FP32/FP64 mixed precision by iterative refinement.
+#include "../../include/newmark.h"
+#include "nm_common.h"
+#include "nm_fft.h"
+#include "nm_passes.h"
+#include "nm_vec.h"
+#include "nm_warm.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstdarg>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+using namespace nm;
+
+struct nm_ctx {
+    // problem
+    int dim = 3, n1 = 0, n2 = 0, n3 = 0, nph = 0;
+    long N = 0, NS = 0, ng = 0;
+    double dt = 0, beta = 0.25, gam = 0.5;
+    std::vector<int64_t> gidx_h;
+    nm_options opt{};
+    SpecParams sp{};
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int route = NM_ROUTE_PROJECTED;
+    // device problem data
+    uint16_t* phase = nullptr;
+    uint8_t* mask = nullptr;
+    int64_t* gidx = nullptr;
+    double* C64 = nullptr;
+    float* C32 = nullptr;
+    double* rho64 = nullptr;
+    float* rho32 = nullptr;
+    double2* tw64 = nullptr;
+    float2* tw32 = nullptr;
+    // scalars and reductions
+    double* scal = nullptr;
+    double* hscal = nullptr; // pinned host mirror
+    double* part_a = nullptr;
+    double* part_b = nullptr;
+    int npart = 0;
+    // FP64 fields (3 x N each)
+    double *u = nullptr, *v = nullptr, *a = nullptr, *ut = nullptr, *b = nullptr, *w = nullptr;
+    double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *uf = nullptr;
+    double2* spec64 = nullptr;
+    // FP32 fields
+    float *d32 = nullptr, *rhs32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    float2* spec32 = nullptr;
+    // Gamma buffers
+    double* Ubuf = nullptr; // dim * max(ng, 1)
+    double* gbuf = nullptr; // dim * max(ng, 1)
+    std::vector<double> G, LU, F_last;
+    std::vector<int> piv;
+    int64_t step = 0;
+    std::string err;
+    std::vector<void*> allocs;
+    nm::WarmNet* warm = nullptr;
+};
+
+namespace {
+
+int fail(nm_ctx* c, int code, const char* fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    if (c) c->err = buf;
+    return code;
+}
+
+#define HIPCHK(c, expr)                                                                                                \
+    do {                                                                                                               \
+        hipError_t e_ = (expr);                                                                                        \
+        if (e_ != hipSuccess) return fail((c), NM_EHIP, "%s: %s", #expr, hipGetErrorString(e_));                      \
+    } while (0)
+#define LCHK(c, expr)                                                                                                  \
+    do {                                                                                                               \
+        int e_ = (expr);                                                                                               \
+        if (e_ != 0) {                                                                                                 \
+            hipError_t he_ = hipGetLastError();                                                                        \
+            return fail((c), e_ == -1 ? NM_EUNSUPPORTED : NM_EHIP, "%s failed (%s)", #expr, hipGetErrorString(he_));   \
+        }                                                                                                              \
+    } while (0)
+#define CHK(expr)                                                                                                      \
+    do {                                                                                                               \
+        int e_ = (expr);                                                                                               \
+        if (e_ != NM_OK) return e_;                                                                                    \
+    } while (0)
+
+template <typename T> int dalloc(nm_ctx* c, T** ptr, size_t count)
+{
+    void* p = nullptr;
+    if (count == 0) count = 1;
+    hipError_t e = hipMalloc(&p, count * sizeof(T));
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(c, NM_ENOMEM, "hipMalloc of %zu bytes failed: %s", count * sizeof(T), hipGetErrorString(e));
+    }
+    c->allocs.push_back(p);
+    *ptr = (T*)p;
+    return NM_OK;
+}
+
+bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
+
+template <typename T> struct Prec;
+template <> struct Prec<double> {
+    static const void* tw(nm_ctx* c) { return c->tw64; }
+    static const void* C(nm_ctx* c) { return c->C64; }
+    static const void* rho(nm_ctx* c) { return c->rho64; }
+    static void* spec(nm_ctx* c) { return c->spec64; }
+};
+template <> struct Prec<float> {
+    static const void* tw(nm_ctx* c) { return c->tw32; }
+    static const void* C(nm_ctx* c) { return c->C32; }
+    static const void* rho(nm_ctx* c) { return c->rho32; }
+    static void* spec(nm_ctx* c) { return c->spec32; }
+};
+
+XFwdArgs xf_args(nm_ctx* c, void* spec)
+{
+    XFwdArgs a{};
+    a.spec = spec;
+    a.scal = c->scal;
+    a.nlines = 3L * c->n2 * c->n3;
+    return a;
+}
+XInvArgs xi_args(nm_ctx* c, void* spec, void* out, const void* aux, const void* rho, const uint8_t* mask,
+                 double* partials)
+{
+    XInvArgs a{};
+    a.spec = spec;
+    a.out = out;
+    a.aux = aux;
+    a.phase = c->phase;
+    a.rho = rho;
+    a.mask = mask;
+    a.partials = partials;
+    a.nlines = 3L * c->n2 * c->n3;
+    a.lines_per_comp = (long)c->n2 * c->n3;
+    a.dim = c->dim;
+    return a;
+}
+
+// q = A p as nine fused passes (see nm_passes.hip).
+template <typename T> int chain_operator(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
+{
+    hipStream_t s = c->stream;
+    void* spec = Prec<T>::spec(c);
+    const void* tw = Prec<T>::tw(c);
+    LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
+    LCHK(c, launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
+    LCHK(c, launch_zspec<T>(ZOP_GRAD, c->sp, c->NS, spec, tw, s));
+    LCHK(c, launch_ypass<T>(+1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s));
+    LCHK(c, launch_xstress<T>(c->n1, spec, (long)c->n2 * c->n3, c->NS, c->phase, Prec<T>::C(c), tw, s));
+    LCHK(c, launch_ypass<T>(-1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s));
+    LCHK(c, launch_zspec<T>(ZOP_DIV, c->sp, c->NS, spec, tw, s));
+    LCHK(c, launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
+    LCHK(c, launch_xinv<T>(XI_OPERATOR, c->n1, ia, tw, s));
+    return NM_OK;
+}
+
+// z = M r: x/y/z forward, pointwise (beta dt^2 K + rhobar I)^-1, inverse.
+template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
+{
+    hipStream_t s = c->stream;
+    void* spec = Prec<T>::spec(c);
+    const void* tw = Prec<T>::tw(c);
+    LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
+    LCHK(c, launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
+    LCHK(c, launch_zspec<T>(ZOP_PRECOND, c->sp, c->NS, spec, tw, s));
+    LCHK(c, launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
+    LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s));
+    return NM_OK;
+}
+
+// q = A x (optionally masked), no reduction.
+template <typename T> int apply_A(nm_ctx* c, const T* x, T* out, const uint8_t* mask)
+{
+    XFwdArgs fa = xf_args(c, Prec<T>::spec(c));
+    fa.src = x;
+    XInvArgs ia = xi_args(c, Prec<T>::spec(c), out, x, Prec<T>::rho(c), mask, nullptr);
+    return chain_operator<T>(c, XF_PLAIN, fa, ia);
+}
+
+int read_scalars(nm_ctx* c)
+{
+    HIPCHK(c, hipMemcpyAsync(c->hscal, c->scal, S_COUNT * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NM_OK;
+}
+
+// ||x||^2 of a 3 x N field (deterministic), returned on the host.
+template <typename T> int norm2(nm_ctx* c, const T* x, double* out)
+{
+    const long n = 3 * c->N;
+    LCHK(c, launch_dot<T>(x, x, n, c->part_a, c->stream));
+    LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_SLOT, 6, c->stream));
+    CHK(read_scalars(c));
+    *out = c->hscal[6];
+    return NM_OK;
+}
+
+struct PcgResult {
+    int iters = 0;
+    double rr = 0;
+    bool converged = false;
+};
+
+// Preconditioned conjugate gradients (Hestenes-Stiefel) on real-space vectors.
+// x: initial guess / solution.  With masked, P A P and P M P on the free dofs.
+template <typename T>
+int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool x_zero, double bref, double tol,
+        int max_iter, int fixed_iters, bool allow_unconverged, PcgResult* res)
+{
+    hipStream_t s = c->stream;
+    const uint8_t* mk = masked ? c->mask : nullptr;
+    const long n = 3 * c->N;
+    void* spec = Prec<T>::spec(c);
+    // r = P (b - A x)
+    if (x_zero) LCHK(c, launch_fill<T>(q, (T)0, n, s));
+    else CHK(apply_A<T>(c, x, q, mk));
+    LCHK(c, launch_residual<T>(rhs, q, r, mk, c->N, 3, c->part_a, s));
+    LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+    CHK(read_scalars(c));
+    double rr = c->hscal[S_RR];
+    res->iters = 0;
+    res->rr = rr;
+    if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite initial residual");
+    if (bref <= 0) bref = 1.0;
+    const double thr = tol * bref;
+    if ((fixed_iters < 0 && std::sqrt(rr) <= thr) || fixed_iters == 0) {
+        res->converged = true;
+        return NM_OK;
+    }
+    const int nb = xinv_blocks(c->n1, 3L * c->n2 * c->n3);
+    // z = P M r, rz = r.z
+    {
+        XFwdArgs fa = xf_args(c, spec);
+        fa.src = r;
+        XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
+        CHK(chain_precond<T>(c, XF_PLAIN, fa, ia));
+        LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_RZ_INIT, 0, s));
+    }
+    int it = 0;
+    for (;;) {
+        // p = z + beta p ; q = P A p ; alpha = rz / p.q
+        {
+            XFwdArgs fa = xf_args(c, spec);
+            fa.src = z;
+            fa.p = p;
+            XInvArgs ia = xi_args(c, spec, q, p, Prec<T>::rho(c), mk, c->part_b);
+            CHK(chain_operator<T>(c, XF_PUPDATE, fa, ia));
+            LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_ALPHA, 0, s));
+        }
+        // x += alpha p ; r -= alpha q ; z = P M r ; beta = r.z_new / r.z_old
+        {
+            XFwdArgs fa = xf_args(c, spec);
+            fa.x = x;
+            fa.r = r;
+            fa.p = p;
+            fa.q = q;
+            fa.partials = c->part_a;
+            XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
+            CHK(chain_precond<T>(c, XF_UPDATE, fa, ia));
+            LCHK(c, launch_reduce(c->part_a, xfwd_blocks(c->n1, 3L * c->n2 * c->n3), c->scal, RED_STORE_RR, 0, s));
+            LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_BETA, 0, s));
+        }
+        it++;
+        CHK(read_scalars(c));
+        rr = c->hscal[S_RR];
+        res->iters = it;
+        res->rr = rr;
+        if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual at iteration %d", it);
+        if (fixed_iters >= 0) {
+            if (it >= fixed_iters) break;
+        } else {
+            if (std::sqrt(rr) <= thr) break;
+            if (it >= max_iter) {
+                if (allow_unconverged) return NM_OK;
+                return fail(c, NM_ENOTCONV, "PCG did not reach tol %.3g in %d iterations (rel %.3g)", tol, max_iter,
+                            std::sqrt(rr) / bref);
+            }
+        }
+    }
+    res->converged = true;
+    return NM_OK;
+}
+
+// ||P (b - A xbar)||, xbar = x on Gamma and 0 elsewhere (reference norm of the projected system).
+int projected_bref(nm_ctx* c, const double* x, double* bref)
+{
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    LCHK(c, launch_fill<double>(c->z, 0.0, n, s));
+    if (c->ng > 0) {
+        LCHK(c, launch_gather_gamma(c->gbuf, x, c->gidx, c->ng, 3, c->N, s));
+        LCHK(c, launch_set_gamma(c->z, c->gidx, c->ng, c->gbuf, 1, 3, c->N, s));
+    }
+    CHK(apply_A<double>(c, c->z, c->q, c->mask));
+    LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+    LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+    CHK(read_scalars(c));
+    *bref = std::sqrt(c->hscal[S_RR]);
+    return NM_OK;
+}
+
+// Mixed precision: FP64 residual r = P(b - A x), FP32 PCG correction, x += d.
+int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st)
+{
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    if (bref <= 0) bref = 1.0;
+    int sweeps = 0, inner = 0;
+    double rr = 0;
+    for (;;) {
+        CHK(apply_A<double>(c, x, c->q, c->mask));
+        LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+        CHK(read_scalars(c));
+        rr = c->hscal[S_RR];
+        if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual in refinement sweep %d", sweeps);
+        if (std::sqrt(rr) <= c->opt.tol * bref) break;
+        if (sweeps >= c->opt.max_sweeps)
+            return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps (rel %.3g)", c->opt.tol,
+                        sweeps, std::sqrt(rr) / bref);
+        LCHK(c, launch_cast_d2f(c->rhs32, c->r, n, s));
+        LCHK(c, launch_fill<float>(c->d32, 0.0f, n, s));
+        PcgResult pr;
+        CHK(pcg<float>(c, c->rhs32, c->d32, c->r32, c->z32, c->p32, c->q32, true, true, std::sqrt(rr),
+                       c->opt.inner_tol, c->opt.max_iter, -1, true, &pr));
+        inner += pr.iters;
+        LCHK(c, launch_add_f2d(x, c->d32, n, s));
+        sweeps++;
+    }
+    if (st) {
+        st->sweeps = sweeps;
+        st->inner_iters = inner;
+        st->relres = std::sqrt(rr) / bref;
+    }
+    return NM_OK;
+}
+
+// Dense LU with partial pivoting (host, row major); 0 or -1 on a zero pivot.
+int lu_factor(std::vector<double>& A, int n, std::vector<int>& piv)
+{
+    piv.resize(n);
+    for (int c = 0; c < n; c++) {
+        int pr = c;
+        double best = std::fabs(A[(size_t)c * n + c]);
+        for (int i = c + 1; i < n; i++) {
+            double v = std::fabs(A[(size_t)i * n + c]);
+            if (v > best) {
+                best = v;
+                pr = i;
+            }
+        }
+        piv[c] = pr;
+        if (best == 0.0) return -1;
+        if (pr != c)
+            for (int j = 0; j < n; j++) std::swap(A[(size_t)c * n + j], A[(size_t)pr * n + j]);
+        const double inv = 1.0 / A[(size_t)c * n + c];
+        for (int i = c + 1; i < n; i++) {
+            double* ri = &A[(size_t)i * n];
+            const double f = ri[c] * inv;
+            ri[c] = f;
+            if (f != 0.0) {
+                const double* rc = &A[(size_t)c * n];
+                for (int j = c + 1; j < n; j++) ri[j] -= f * rc[j];
+            }
+        }
+    }
+    return 0;
+}
+
+void lu_solve(const std::vector<double>& LU, int n, const std::vector<int>& piv, double* b)
+{
+    for (int c = 0; c < n; c++)
+        if (piv[c] != c) std::swap(b[c], b[piv[c]]);
+    for (int i = 0; i < n; i++) {
+        double s = b[i];
+        for (int j = 0; j < i; j++) s -= LU[(size_t)i * n + j] * b[j];
+        b[i] = s;
+    }
+    for (int i = n - 1; i >= 0; i--) {
+        double s = b[i];
+        for (int j = i + 1; j < n; j++) s -= LU[(size_t)i * n + j] * b[j];
+        b[i] = s / LU[(size_t)i * n + i];
+    }
+}
+
+// G from the unit-force solves of eq. (solve_green): column d p + j is the
+// Gamma trace of A^-1 (e_j at x_p); rows ordered d q + i.
+int build_green(nm_ctx* c)
+{
+    hipStream_t s = c->stream;
+    const int d = c->dim;
+    const long n = 3 * c->N;
+    const int nd = (int)(d * c->ng);
+    c->G.assign((size_t)nd * nd, 0.0);
+    std::vector<double> col(3 * c->ng);
+    double unit[3];
+    for (long pnt = 0; pnt < c->ng; pnt++)
+        for (int j = 0; j < d; j++) {
+            LCHK(c, launch_fill<double>(c->b, 0.0, n, s));
+            unit[0] = unit[1] = unit[2] = 0.0;
+            unit[j] = 1.0;
+            HIPCHK(c, hipMemcpyAsync(c->Ubuf, unit, 3 * sizeof(double), hipMemcpyHostToDevice, s));
+            LCHK(c, launch_set_gamma(c->b, c->gidx + pnt, 1, c->Ubuf, 0, 3, c->N, s));
+            LCHK(c, launch_fill<double>(c->w, 0.0, n, s));
+            PcgResult pr;
+            CHK(pcg<double>(c, c->b, c->w, c->r, c->z, c->p, c->q, false, true, 1.0, c->opt.green_tol,
+                            c->opt.max_iter, -1, false, &pr));
+            LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));
+            HIPCHK(c, hipMemcpyAsync(col.data(), c->gbuf, 3 * c->ng * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            for (long qq = 0; qq < c->ng; qq++)
+                for (int i = 0; i < d; i++) c->G[(size_t)(d * qq + i) * nd + (d * pnt + j)] = col[3 * qq + i];
+        }
+    c->LU = c->G;
+    if (lu_factor(c->LU, nd, c->piv) != 0) return fail(c, NM_ESINGULAR, "zero pivot in the Green matrix");
+    return NM_OK;
+}
+
+void fill_twiddles(std::vector<double2>& t64)
+{
+    t64.assign(kTwiddleCount, double2{0, 0});
+    for (int L = 2; L <= 1024; L *= 2)
+        for (int i = 0; i < L; i++) {
+            const double ang = -2.0 * M_PI * (double)i / (double)L;
+            t64[tw_offset(L) + i] = double2{std::cos(ang), std::sin(ang)};
+        }
+}
+
+template <typename T> int precond_impl(nm_ctx* c, const T* r, T* z)
+{
+    XFwdArgs fa = xf_args(c, Prec<T>::spec(c));
+    fa.src = r;
+    XInvArgs ia = xi_args(c, Prec<T>::spec(c), z, r, Prec<T>::rho(c), nullptr, nullptr);
+    return chain_precond<T>(c, XF_PLAIN, fa, ia);
+}
+
+} // namespace
+
+extern "C" {
+
+const char* nm_last_error(const nm_ctx* ctx) { return ctx ? ctx->err.c_str() : "null context"; }
+
+void nm_destroy(nm_ctx* c)
+{
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->warm) nm::warm_destroy(c->warm);
+    for (void* p : c->allocs) (void)hipFree(p);
+    if (c->hscal) (void)hipHostFree(c->hscal);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    delete c;
+}
+
+static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
+{
+    if (!pb || !op) return fail(c, NM_EINVAL, "null problem or options");
+    if (pb->dim != 2 && pb->dim != 3) return fail(c, NM_EUNSUPPORTED, "dim must be 2 or 3");
+    c->dim = pb->dim;
+    c->n1 = pb->n[0];
+    c->n2 = pb->n[1];
+    c->n3 = pb->n[2];
+    if (!pow2_in(c->n1, 8, 512) || !pow2_in(c->n2, 8, 512))
+        return fail(c, NM_EUNSUPPORTED, "n1, n2 must be powers of two in [8, 512]");
+    if (c->dim == 2 ? c->n3 != 1 : !pow2_in(c->n3, 8, 512))
+        return fail(c, NM_EUNSUPPORTED, "n3 must be 1 in 2D and a power of two in [8, 512] in 3D");
+    c->N = (long)c->n1 * c->n2 * c->n3;
+    c->NS = c->N / 2;
+    if (pb->n_phases < 1 || pb->n_phases > 65536) return fail(c, NM_EINVAL, "n_phases out of range");
+    c->nph = pb->n_phases;
+    if (!pb->phase_id || !pb->C_voigt || !pb->rho) return fail(c, NM_EINVAL, "null material arrays");
+    if (!(pb->dt > 0) || !(pb->beta > 0) || !std::isfinite(pb->dt)) return fail(c, NM_EINVAL, "bad dt or beta");
+    c->dt = pb->dt;
+    c->beta = pb->beta;
+    c->gam = pb->gamma_nm;
+    if (pb->n_gamma < 0 || (pb->n_gamma > 0 && !pb->gamma_idx)) return fail(c, NM_EINVAL, "bad Gamma set");
+    c->ng = pb->n_gamma;
+    c->gidx_h.assign(pb->gamma_idx, pb->gamma_idx + c->ng);
+    for (long i = 0; i < c->ng; i++) {
+        if (c->gidx_h[i] < 0 || c->gidx_h[i] >= c->N) return fail(c, NM_EINVAL, "Gamma index %ld out of range", i);
+        if (i > 0 && c->gidx_h[i] <= c->gidx_h[i - 1])
+            return fail(c, NM_EINVAL, "Gamma indices must be sorted and unique");
+    }
+    c->opt = *op;
+    if (!(c->opt.tol > 0) || c->opt.max_iter <= 0) return fail(c, NM_EINVAL, "tol and max_iter must be positive");
+    if (c->opt.precision == NM_PREC_MIXED) {
+        if (!(c->opt.inner_tol > 0)) c->opt.inner_tol = 1e-4;
+        if (c->opt.max_sweeps <= 0) c->opt.max_sweeps = 20;
+    }
+    if (!(c->opt.green_tol > 0)) c->opt.green_tol = c->opt.tol * 1e-2;
+    c->route = c->opt.route == NM_ROUTE_GREEN ? NM_ROUTE_GREEN : NM_ROUTE_PROJECTED;
+    if (c->route == NM_ROUTE_GREEN && c->opt.precision == NM_PREC_MIXED)
+        return fail(c, NM_EUNSUPPORTED, "mixed precision runs on the projected route");
+    if (c->opt.warm_start < NM_WS_COLD || c->opt.warm_start > NM_WS_LEARNED)
+        return fail(c, NM_EINVAL, "unknown warm start");
+
+    // host-side material checks and reference medium (volume averages)
+    std::vector<long> count(c->nph, 0);
+    for (long v = 0; v < c->N; v++) {
+        if (pb->phase_id[v] >= c->nph) return fail(c, NM_EINVAL, "phase id out of range at voxel %ld", v);
+        count[pb->phase_id[v]]++;
+    }
+    c->sp.L1 = pb->L[0];
+    c->sp.L2 = pb->L[1];
+    c->sp.L3 = c->dim == 2 ? 1.0 : pb->L[2];
+    c->sp.n1 = c->n1;
+    c->sp.n2 = c->n2;
+    c->sp.n3 = c->n3;
+    c->sp.dim = c->dim;
+    c->sp.inv_ntot = 1.0 / (double)c->N;
+    c->sp.bdt2 = c->beta * c->dt * c->dt;
+    c->sp.rhobar = 0;
+    for (int k = 0; k < 21; k++) c->sp.Cbar[k] = 0;
+    for (int g = 0; g < c->nph; g++) {
+        if (!(pb->rho[g] > 0)) return fail(c, NM_EINVAL, "density of phase %d must be positive", g);
+        const double wgt = (double)count[g] / (double)c->N;
+        c->sp.rhobar += wgt * pb->rho[g];
+        for (int k = 0; k < 21; k++) {
+            if (!std::isfinite(pb->C_voigt[21 * g + k])) return fail(c, NM_EINVAL, "non-finite stiffness");
+            c->sp.Cbar[k] += wgt * pb->C_voigt[21 * g + k];
+        }
+    }
+    if (!(pb->L[0] > 0) || !(pb->L[1] > 0) || (c->dim == 3 && !(pb->L[2] > 0)))
+        return fail(c, NM_EINVAL, "box lengths must be positive");
+
+    // stream
+    if (c->stream == nullptr) {
+        HIPCHK(c, hipStreamCreate(&c->stream));
+        c->own_stream = true;
+    }
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    // device problem data
+    CHK(dalloc(c, &c->phase, c->N));
+    HIPCHK(c, hipMemcpyAsync(c->phase, pb->phase_id, c->N * sizeof(uint16_t), hipMemcpyHostToDevice, s));
+    CHK(dalloc(c, &c->mask, c->N));
+    {
+        std::vector<uint8_t> m(c->N, 0);
+        for (long i = 0; i < c->ng; i++) m[c->gidx_h[i]] = 1;
+        HIPCHK(c, hipMemcpy(c->mask, m.data(), c->N, hipMemcpyHostToDevice));
+    }
+    CHK(dalloc(c, &c->gidx, c->ng));
+    if (c->ng) HIPCHK(c, hipMemcpy(c->gidx, c->gidx_h.data(), c->ng * sizeof(int64_t), hipMemcpyHostToDevice));
+    {
+        std::vector<float> c32(21 * (size_t)c->nph), r32(c->nph);
+        for (size_t i = 0; i < c32.size(); i++) c32[i] = (float)pb->C_voigt[i];
+        for (int g = 0; g < c->nph; g++) r32[g] = (float)pb->rho[g];
+        CHK(dalloc(c, &c->C64, 21 * (size_t)c->nph));
+        CHK(dalloc(c, &c->C32, 21 * (size_t)c->nph));
+        CHK(dalloc(c, &c->rho64, c->nph));
+        CHK(dalloc(c, &c->rho32, c->nph));
+        HIPCHK(c, hipMemcpy(c->C64, pb->C_voigt, 21 * c->nph * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->C32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->rho64, pb->rho, c->nph * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->rho32, r32.data(), r32.size() * sizeof(float), hipMemcpyHostToDevice));
+    }
+    {
+        std::vector<double2> t64;
+        fill_twiddles(t64);
+        std::vector<float2> t32(t64.size());
+        for (size_t i = 0; i < t64.size(); i++) t32[i] = float2{(float)t64[i].x, (float)t64[i].y};
+        CHK(dalloc(c, &c->tw64, t64.size()));
+        CHK(dalloc(c, &c->tw32, t32.size()));
+        HIPCHK(c, hipMemcpy(c->tw64, t64.data(), t64.size() * sizeof(double2), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->tw32, t32.data(), t32.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    CHK(dalloc(c, &c->scal, S_COUNT));
+    HIPCHK(c, hipMemset(c->scal, 0, S_COUNT * sizeof(double)));
+    HIPCHK(c, hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocDefault));
+    c->npart = std::max(xfwd_blocks(c->n1, 3L * c->n2 * c->n3), vec_blocks(n));
+    CHK(dalloc(c, &c->part_a, c->npart));
+    CHK(dalloc(c, &c->part_b, c->npart));
+    // fields
+    double** f64[] = {&c->u, &c->v, &c->a, &c->ut, &c->b, &c->w, &c->r, &c->z, &c->p, &c->q};
+    for (double** f : f64) {
+        CHK(dalloc(c, f, n));
+        LCHK(c, launch_fill<double>(*f, 0.0, n, s));
+    }
+    CHK(dalloc(c, &c->spec64, 6 * c->NS));
+    if (c->route == NM_ROUTE_GREEN) {
+        CHK(dalloc(c, &c->uf, n));
+        LCHK(c, launch_fill<double>(c->uf, 0.0, n, s));
+    }
+    CHK(dalloc(c, &c->spec32, 6 * c->NS));
+    if (c->opt.precision == NM_PREC_MIXED) {
+        float** f32[] = {&c->d32, &c->rhs32, &c->r32, &c->z32, &c->p32, &c->q32};
+        for (float** f : f32) {
+            CHK(dalloc(c, f, n));
+            LCHK(c, launch_fill<float>(*f, 0.0f, n, s));
+        }
+    }
+    CHK(dalloc(c, &c->Ubuf, 3 * std::max<long>(c->ng, 1)));
+    CHK(dalloc(c, &c->gbuf, 3 * std::max<long>(c->ng, 1)));
+    c->F_last.assign(c->dim * c->ng, 0.0);
+    // initial state (host dim x N -> device 3 x N)
+    if (pb->u0) HIPCHK(c, hipMemcpy(c->u, pb->u0, c->dim * c->N * sizeof(double), hipMemcpyHostToDevice));
+    if (pb->v0) HIPCHK(c, hipMemcpy(c->v, pb->v0, c->dim * c->N * sizeof(double), hipMemcpyHostToDevice));
+    if (pb->u0) {
+        // a0 = div(C : grad^s u0) / rho
+        CHK(apply_A<double>(c, c->u, c->q, nullptr));
+        LCHK(c, launch_accel0(c->a, c->u, c->q, c->phase, c->rho64, c->N, 3, c->sp.bdt2, s));
+    }
+    if (c->route == NM_ROUTE_GREEN && c->ng > 0) CHK(build_green(c));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return NM_OK;
+}
+
+int nm_newmark_init(const nm_problem* pb, const nm_options* op, void* hip_stream, nm_ctx** out)
+{
+    if (!out) return NM_EINVAL;
+    *out = nullptr;
+    nm_ctx* c = new nm_ctx();
+    c->stream = (hipStream_t)hip_stream;
+    int st = init_impl(c, pb, op);
+    *out = c; // returned even on error so that nm_last_error can be read; caller destroys
+    return st;
+}
+
+static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats* st)
+{
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    const int d = c->dim;
+    const long nU = per_point ? d * c->ng : d;
+    if (c->ng > 0 && !U_n) return fail(c, NM_EINVAL, "null prescribed displacement");
+    std::vector<double> U3(per_point ? 3 * c->ng : 3, 0.0);
+    for (long i = 0; c->ng > 0 && i < nU; i++) {
+        if (!std::isfinite(U_n[i])) return fail(c, NM_ENAN, "non-finite prescribed displacement");
+        if (per_point) U3[3 * (i / d) + i % d] = U_n[i];
+        else U3[i] = U_n[i];
+    }
+    if (c->ng > 0)
+        HIPCHK(c, hipMemcpyAsync(c->Ubuf, U3.data(), U3.size() * sizeof(double), hipMemcpyHostToDevice, s));
+    auto t0 = std::chrono::steady_clock::now();
+    // predictor and right-hand side, eq. (Fourier_ND_b)
+    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    // initial guess
+    double t_warm = 0;
+    switch (c->opt.warm_start) {
+    case NM_WS_COLD: LCHK(c, launch_fill<double>(c->w, 0.0, n, s)); break;
+    case NM_WS_TAYLOR: LCHK(c, launch_taylor(c->w, c->u, c->v, c->a, n, c->dt, s)); break;
+    case NM_WS_LEARNED: {
+        if (!c->warm) return fail(c, NM_EINVAL, "learned warm start requested but no network weights are set");
+        auto tw0 = std::chrono::steady_clock::now();
+        int e = nm::warm_predict(c->warm, c->u, c->v, c->a, c->w, c->dt, s);
+        if (e) return fail(c, NM_EHIP, "warm-start network failed");
+        HIPCHK(c, hipStreamSynchronize(s));
+        t_warm = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw0).count();
+        break;
+    }
+    default: LCHK(c, launch_copy<double>(c->w, c->u, n, s)); break;
+    }
+    nm_step_stats local{};
+    local.iters[1] = 0;
+    if (c->route == NM_ROUTE_GREEN && c->ng > 0) {
+        const int nd = (int)(d * c->ng);
+        double bn;
+        CHK(norm2<double>(c, c->b, &bn));
+        PcgResult r1, r2;
+        CHK(pcg<double>(c, c->b, c->w, c->r, c->z, c->p, c->q, false, false, std::sqrt(bn), c->opt.tol,
+                        c->opt.max_iter, -1, false, &r1));
+        // V = U - u_b on Gamma ; F = G^-1 V / (beta dt^2)   (eqs. Vt, L-determination_ND)
+        std::vector<double> g3(3 * c->ng), F(nd);
+        LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));
+        HIPCHK(c, hipMemcpyAsync(g3.data(), c->gbuf, g3.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (long pnt = 0; pnt < c->ng; pnt++)
+            for (int j = 0; j < d; j++) F[d * pnt + j] = (per_point ? U3[3 * pnt + j] : U3[j]) - g3[3 * pnt + j];
+        lu_solve(c->LU, nd, c->piv, F.data());
+        double fn = 0;
+        std::vector<double> F3(3 * c->ng, 0.0);
+        for (long pnt = 0; pnt < c->ng; pnt++)
+            for (int j = 0; j < d; j++) {
+                const double f = F[d * pnt + j] / c->sp.bdt2;
+                F[d * pnt + j] = f;
+                F3[3 * pnt + j] = f;
+                fn += f * f;
+            }
+        // f = F on Gamma (reuse b, no longer needed) ; A u_f = f from the previous u_f
+        LCHK(c, launch_fill<double>(c->b, 0.0, n, s));
+        HIPCHK(c, hipMemcpyAsync(c->gbuf, F3.data(), F3.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        LCHK(c, launch_set_gamma(c->b, c->gidx, c->ng, c->gbuf, 1, 3, c->N, s));
+        CHK(pcg<double>(c, c->b, c->uf, c->r, c->z, c->p, c->q, false, false, std::sqrt(fn), c->opt.tol,
+                        c->opt.max_iter, -1, false, &r2));
+        // u_n = u_b + beta dt^2 u_f   (eq. Sol_Real_ND)
+        LCHK(c, launch_axpby<double>(c->w, c->w, c->uf, c->sp.bdt2, n, s));
+        local.iters[0] = r1.iters;
+        local.iters[1] = r2.iters;
+        local.relres = std::sqrt(r1.rr) / std::sqrt(bn);
+        c->F_last = F;
+    } else {
+        if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
+        double bref;
+        CHK(projected_bref(c, c->w, &bref));
+        if (c->opt.precision == NM_PREC_MIXED) {
+            CHK(solve_mixed(c, c->w, bref, &local));
+        } else {
+            PcgResult r1;
+            CHK(pcg<double>(c, c->b, c->w, c->r, c->z, c->p, c->q, true, false, bref, c->opt.tol, c->opt.max_iter,
+                            -1, false, &r1));
+            local.iters[0] = r1.iters;
+            local.relres = std::sqrt(r1.rr) / (bref > 0 ? bref : 1.0);
+            if (c->opt.true_residual) {
+                CHK(apply_A<double>(c, c->w, c->q, c->mask));
+                LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+                LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+                CHK(read_scalars(c));
+                local.relres = std::sqrt(c->hscal[S_RR]) / (bref > 0 ? bref : 1.0);
+            }
+        }
+        if (c->opt.compute_reaction && c->ng > 0) {
+            // F = (A u - b)|Gamma / (beta dt^2)
+            CHK(apply_A<double>(c, c->w, c->q, nullptr));
+            LCHK(c, launch_axpby<double>(c->r, c->q, c->b, -1.0, n, s));
+            LCHK(c, launch_gather_gamma(c->gbuf, c->r, c->gidx, c->ng, 3, c->N, s));
+            std::vector<double> g3(3 * c->ng);
+            HIPCHK(c, hipMemcpyAsync(g3.data(), c->gbuf, g3.size() * sizeof(double), hipMemcpyDeviceToHost, s));
+            HIPCHK(c, hipStreamSynchronize(s));
+            for (long pnt = 0; pnt < c->ng; pnt++)
+                for (int j = 0; j < d; j++) c->F_last[d * pnt + j] = g3[3 * pnt + j] / c->sp.bdt2;
+        }
+    }
+    // corrector, then u <- u_n (pointer swap)
+    LCHK(c, launch_corrector(c->w, c->ut, c->v, c->a, n, c->dt, c->beta, c->gam, s));
+    std::swap(c->u, c->w);
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->step++;
+    local.t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    local.t_warm_ms = t_warm;
+    if (st) *st = local;
+    return NM_OK;
+}
+
+int nm_newmark_step(nm_ctx* c, const double* U_n, int per_point, nm_step_stats* st)
+{
+    if (!c) return NM_EINVAL;
+    return step_impl(c, U_n, per_point, st);
+}
+
+int nm_apply_operator(nm_ctx* c, const void* u_dev, void* Au_dev, int dtype)
+{
+    if (!c) return NM_EINVAL;
+    if (!u_dev || !Au_dev || u_dev == Au_dev) return fail(c, NM_EINVAL, "bad buffers");
+    if (dtype == NM_FP64) return apply_A<double>(c, (const double*)u_dev, (double*)Au_dev, nullptr);
+    if (dtype == NM_FP32) return apply_A<float>(c, (const float*)u_dev, (float*)Au_dev, nullptr);
+    return fail(c, NM_EINVAL, "dtype must be NM_FP64 or NM_FP32");
+}
+
+int nm_precond_apply(nm_ctx* c, const void* r_dev, void* z_dev, int dtype)
+{
+    if (!c) return NM_EINVAL;
+    if (!r_dev || !z_dev || r_dev == z_dev) return fail(c, NM_EINVAL, "bad buffers");
+    if (dtype == NM_FP64) return precond_impl<double>(c, (const double*)r_dev, (double*)z_dev);
+    if (dtype == NM_FP32) return precond_impl<float>(c, (const float*)r_dev, (float*)z_dev);
+    return fail(c, NM_EINVAL, "dtype must be NM_FP64 or NM_FP32");
+}
+
+int nm_pcg_solve(nm_ctx* c, const void* b_dev, void* x_dev, int masked, double tol, int max_iter, int fixed_iters,
+                 int* iters, double* relres)
+{
+    if (!c) return NM_EINVAL;
+    if (!b_dev || !x_dev || b_dev == x_dev) return fail(c, NM_EINVAL, "bad buffers");
+    if (!(tol > 0) || max_iter <= 0) return fail(c, NM_EINVAL, "bad tolerance or max_iter");
+    double bref;
+    // the projected reference norm reads c->b, so stage the right-hand side there
+    HIPCHK(c, hipMemcpyAsync(c->b, b_dev, 3 * c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    if (masked) {
+        CHK(projected_bref(c, (const double*)x_dev, &bref));
+    } else {
+        double bn;
+        CHK(norm2<double>(c, c->b, &bn));
+        bref = std::sqrt(bn);
+    }
+    PcgResult pr;
+    CHK(pcg<double>(c, c->b, (double*)x_dev, c->r, c->z, c->p, c->q, masked != 0, false, bref, tol, max_iter,
+                    fixed_iters, false, &pr));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (iters) *iters = pr.iters;
+    if (relres) *relres = std::sqrt(pr.rr) / (bref > 0 ? bref : 1.0);
+    return NM_OK;
+}
+
+int nm_get_state(const nm_ctx* cc, double* u, double* v, double* a, double* F_gamma, int64_t* step)
+{
+    nm_ctx* c = const_cast<nm_ctx*>(cc);
+    if (!c) return NM_EINVAL;
+    const size_t bytes = c->dim * c->N * sizeof(double);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (u) HIPCHK(c, hipMemcpy(u, c->u, bytes, hipMemcpyDeviceToHost));
+    if (v) HIPCHK(c, hipMemcpy(v, c->v, bytes, hipMemcpyDeviceToHost));
+    if (a) HIPCHK(c, hipMemcpy(a, c->a, bytes, hipMemcpyDeviceToHost));
+    if (F_gamma && !c->F_last.empty()) std::memcpy(F_gamma, c->F_last.data(), c->F_last.size() * sizeof(double));
+    if (step) *step = c->step;
+    return NM_OK;
+}
+
+int nm_set_state(nm_ctx* c, const double* u, const double* v, const double* a, int64_t step)
+{
+    if (!c) return NM_EINVAL;
+    if (!u || !v || !a) return fail(c, NM_EINVAL, "u, v and a are required");
+    const size_t bytes = c->dim * c->N * sizeof(double);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    HIPCHK(c, hipMemcpy(c->u, u, bytes, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->v, v, bytes, hipMemcpyHostToDevice));
+    HIPCHK(c, hipMemcpy(c->a, a, bytes, hipMemcpyHostToDevice));
+    c->step = step;
+    return NM_OK;
+}
+
+int nm_state_device_ptrs(nm_ctx* c, void** u, void** v, void** a)
+{
+    if (!c) return NM_EINVAL;
+    if (u) *u = c->u;
+    if (v) *v = c->v;
+    if (a) *a = c->a;
+    return NM_OK;
+}
+
+void* nm_get_stream(nm_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+int nm_green_matrix(const nm_ctx* c, double* G)
+{
+    if (!c || !G) return NM_EINVAL;
+    if (c->G.empty()) return NM_EINVAL;
+    std::memcpy(G, c->G.data(), c->G.size() * sizeof(double));
+    return NM_OK;
+}
+
+} // extern "C"

@@ -1,0 +1,49 @@
+// Host launchers of the pointwise vector, reduction and Newmark kernels (nm_vec.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace nm {
+
+enum ReduceAction { RED_STORE_RR = 0, RED_ALPHA = 1, RED_RZ_INIT = 2, RED_BETA = 3, RED_STORE_SLOT = 4 };
+
+// Deterministic sum of n per-block partials into the scalar block, then the action.
+int launch_reduce(const double* partials, int n, double* scal, int action, int slot, hipStream_t s);
+
+// Number of partials written by the grid-stride kernels below.
+int vec_blocks(long n);
+
+// r = b - q (masked entries -> 0), partial sums of r.r.
+template <typename T>
+int launch_residual(const T* b, const T* q, T* r, const uint8_t* mask, long N, int ncomp, double* partials,
+                    hipStream_t s);
+// out = a + c * b.
+template <typename T> int launch_axpby(T* out, const T* a, const T* b, double c, long n, hipStream_t s);
+// y (FP32) = (float) x (FP64);  x64 += (double) d32
+int launch_cast_d2f(float* y, const double* x, long n, hipStream_t s);
+int launch_add_f2d(double* x, const float* d, long n, hipStream_t s);
+template <typename T> int launch_fill(T* x, T v, long n, hipStream_t s);
+template <typename T> int launch_copy(T* dst, const T* src, long n, hipStream_t s);
+// partial sums of a.b (FP64 accumulation)
+template <typename T> int launch_dot(const T* a, const T* b, long n, double* partials, hipStream_t s);
+
+// x[j*N + gidx[p]] = (per_point ? U[dim*p + j] : U[j]) for p < ng, j < dim
+int launch_set_gamma(double* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N,
+                     hipStream_t s);
+// out[dim*p + j] = x[j*N + gidx[p]]
+int launch_gather_gamma(double* out, const double* x, const int64_t* gidx, long ng, int dim, long N, hipStream_t s);
+
+// Newmark predictor: ut = u + dt v + dt^2 (1/2 - beta) a ; b = rho(phase) ut
+int launch_predictor(const double* u, const double* v, const double* a, double* ut, double* b,
+                     const uint16_t* phase, const double* rho, long N, int ncomp, double dt, double beta,
+                     hipStream_t s);
+// Newmark corrector: an = (un - ut)/(beta dt^2); v += dt((1-g) a + g an); a = an
+int launch_corrector(const double* un, const double* ut, double* v, double* a, long n, double dt, double beta,
+                     double gam, hipStream_t s);
+// Initial acceleration from q = A u0: a0 = (rho u0 - q) / (beta dt^2 rho) = div(C : grad^s u0) / rho
+int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* phase, const double* rho, long N,
+                  int ncomp, double bdt2, hipStream_t s);
+// Second-order Taylor start: x = u + dt v + dt^2/2 a
+int launch_taylor(double* x, const double* u, const double* v, const double* a, long n, double dt, hipStream_t s);
+
+} // namespace nm

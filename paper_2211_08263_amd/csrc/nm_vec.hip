@@ -1,0 +1,281 @@
+// Pointwise vector, reduction and Newmark kernels (grid-stride, coalesced SoA).
+#include "nm_common.h"
+#include "nm_passes.h"
+#include "nm_vec.h"
+
+namespace nm {
+
+constexpr int kVecBlocksMax = 2048;
+
+int vec_blocks(long n)
+{
+    long b = (n + kBlock * 4 - 1) / (kBlock * 4);
+    if (b < 1) b = 1;
+    return (int)(b < kVecBlocksMax ? b : kVecBlocksMax);
+}
+
+__device__ __forceinline__ double wave_sum_v(double v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ double block_sum_v(double v)
+{
+    __shared__ double sh[16];
+    v = wave_sum_v(v);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int i = 0; i < (int)(blockDim.x + 63) / 64; i++) s += sh[i];
+    return s;
+}
+
+// One block of 1024 threads: thread i sums partials i, i+1024, ... in order.
+__global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part, int n, double* scal, int action,
+                                                 int slot)
+{
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
+    const double s = block_sum_v(v);
+    if (threadIdx.x == 0) {
+        switch (action) {
+        case RED_STORE_RR: scal[S_RR] = s; break;
+        case RED_ALPHA:
+            scal[S_PQ] = s;
+            scal[S_ALPHA] = scal[S_RZ] / s;
+            break;
+        case RED_RZ_INIT:
+            scal[S_RZ] = s;
+            scal[S_FIRST] = 1.0;
+            break;
+        case RED_BETA:
+            scal[S_BETA] = s / scal[S_RZ];
+            scal[S_RZ] = s;
+            scal[S_FIRST] = 0.0;
+            break;
+        default: scal[slot] = s; break;
+        }
+    }
+}
+
+int launch_reduce(const double* partials, int n, double* scal, int action, int slot, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partials, n, scal, action, slot);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ b, const T* __restrict__ q, T* __restrict__ r,
+                                                     const uint8_t* __restrict__ mask, long N, long n,
+                                                     double* partials)
+{
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        T v = b[i] - q[i];
+        if (mask && mask[i % N]) v = 0;
+        r[i] = v;
+        acc += (double)v * (double)v;
+    }
+    const double s = block_sum_v(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+
+template <typename T>
+int launch_residual(const T* b, const T* q, T* r, const uint8_t* mask, long N, int ncomp, double* partials,
+                    hipStream_t s)
+{
+    const long n = N * ncomp;
+    hipLaunchKernelGGL((k_residual<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, q, r, mask, N, n, partials);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpby(T* out, const T* a, const T* b, double c, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        out[i] = a[i] + (T)c * b[i];
+}
+template <typename T> int launch_axpby(T* out, const T* a, const T* b, double c, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_axpby<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, out, a, b, c, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_cast_d2f(float* y, const double* x, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        y[i] = (float)x[i];
+}
+int launch_cast_d2f(float* y, const double* x, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_cast_d2f, dim3(vec_blocks(n)), dim3(kBlock), 0, s, y, x, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_add_f2d(double* x, const float* d, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] += (double)d[i];
+}
+int launch_add_f2d(double* x, const float* d, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_f2d, dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, d, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T> __global__ __launch_bounds__(kBlock) void k_fill(T* x, T v, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) x[i] = v;
+}
+template <typename T> int launch_fill(T* x, T v, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_fill<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, v, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T> __global__ __launch_bounds__(kBlock) void k_copy(T* d, const T* s, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) d[i] = s[i];
+}
+template <typename T> int launch_copy(T* dst, const T* src, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_copy<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, dst, src, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_dot(const T* __restrict__ a, const T* __restrict__ b, long n,
+                                                double* partials)
+{
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        acc += (double)a[i] * (double)b[i];
+    const double s = block_sum_v(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+template <typename T> int launch_dot(const T* a, const T* b, long n, double* partials, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_dot<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, b, n, partials);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ void k_set_gamma(double* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ng * dim) return;
+    const long p = i / dim;
+    const int j = (int)(i % dim);
+    x[j * N + gidx[p]] = per_point ? U[i] : U[j];
+}
+int launch_set_gamma(double* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N,
+                     hipStream_t s)
+{
+    if (ng == 0) return 0;
+    const long n = ng * dim;
+    hipLaunchKernelGGL(k_set_gamma, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, gidx, ng, U,
+                       per_point, dim, N);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ void k_gather_gamma(double* out, const double* x, const int64_t* gidx, long ng, int dim, long N)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= ng * dim) return;
+    const long p = i / dim;
+    const int j = (int)(i % dim);
+    out[i] = x[j * N + gidx[p]];
+}
+int launch_gather_gamma(double* out, const double* x, const int64_t* gidx, long ng, int dim, long N, hipStream_t s)
+{
+    if (ng == 0) return 0;
+    const long n = ng * dim;
+    hipLaunchKernelGGL(k_gather_gamma, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, out, x, gidx,
+                       ng, dim, N);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_predictor(const double* __restrict__ u, const double* __restrict__ v,
+                                                      const double* __restrict__ a, double* __restrict__ ut,
+                                                      double* __restrict__ b, const uint16_t* __restrict__ phase,
+                                                      const double* __restrict__ rho, long N, long n, double dt,
+                                                      double c2)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double w = u[i] + dt * v[i] + c2 * a[i];
+        ut[i] = w;
+        b[i] = rho[phase[i % N]] * w;
+    }
+}
+int launch_predictor(const double* u, const double* v, const double* a, double* ut, double* b, const uint16_t* phase,
+                     const double* rho, long N, int ncomp, double dt, double beta, hipStream_t s)
+{
+    const long n = N * ncomp;
+    hipLaunchKernelGGL(k_predictor, dim3(vec_blocks(n)), dim3(kBlock), 0, s, u, v, a, ut, b, phase, rho, N, n, dt,
+                       dt * dt * (0.5 - beta));
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_corrector(const double* __restrict__ un, const double* __restrict__ ut,
+                                                      double* __restrict__ v, double* __restrict__ a, long n,
+                                                      double dt, double inv_bdt2, double gam)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double an = (un[i] - ut[i]) * inv_bdt2;
+        v[i] = v[i] + dt * ((1.0 - gam) * a[i] + gam * an);
+        a[i] = an;
+    }
+}
+int launch_corrector(const double* un, const double* ut, double* v, double* a, long n, double dt, double beta,
+                     double gam, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_corrector, dim3(vec_blocks(n)), dim3(kBlock), 0, s, un, ut, v, a, n, dt,
+                       1.0 / (beta * dt * dt), gam);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_accel0(double* a, const double* u0, const double* q,
+                                                   const uint16_t* phase, const double* rho, long N, long n,
+                                                   double bdt2)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double r = rho[phase[i % N]];
+        a[i] = (r * u0[i] - q[i]) / (bdt2 * r);
+    }
+}
+int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* phase, const double* rho, long N,
+                  int ncomp, double bdt2, hipStream_t s)
+{
+    const long n = N * ncomp;
+    hipLaunchKernelGGL(k_accel0, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, u0, q, phase, rho, N, n, bdt2);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_taylor(double* x, const double* u, const double* v, const double* a, long n,
+                                                   double dt)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = u[i] + dt * v[i] + 0.5 * dt * dt * a[i];
+}
+int launch_taylor(double* x, const double* u, const double* v, const double* a, long n, double dt, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_taylor, dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, u, v, a, n, dt);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+template int launch_residual<double>(const double*, const double*, double*, const uint8_t*, long, int, double*,
+                                     hipStream_t);
+template int launch_residual<float>(const float*, const float*, float*, const uint8_t*, long, int, double*,
+                                    hipStream_t);
+template int launch_axpby<double>(double*, const double*, const double*, double, long, hipStream_t);
+template int launch_axpby<float>(float*, const float*, const float*, double, long, hipStream_t);
+template int launch_fill<double>(double*, double, long, hipStream_t);
+template int launch_fill<float>(float*, float, long, hipStream_t);
+template int launch_copy<double>(double*, const double*, long, hipStream_t);
+template int launch_copy<float>(float*, const float*, long, hipStream_t);
+template int launch_dot<double>(const double*, const double*, long, double*, hipStream_t);
+template int launch_dot<float>(const float*, const float*, long, double*, hipStream_t);
+
+} // namespace nm

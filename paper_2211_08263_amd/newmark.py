@@ -1,0 +1,267 @@
+"""Python binding of libnewmark.so (the C ABI of include/newmark.h).
+
+Argument marshalling only: every step of the solver runs in the library's
+HIP kernels.  Device buffers are torch tensors (used for device memory only).
+The binding refuses to run without the built library; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libnewmark.so")
+
+NM_OK, NM_EINVAL, NM_EUNSUPPORTED, NM_ENOMEM, NM_ENOTCONV, NM_ESINGULAR, NM_ENAN, NM_EHIP = 0, -1, -2, -3, -4, -5, -6, -7
+NM_FP64, NM_FP32 = 0, 1
+PREC_FP64, PREC_MIXED = 0, 1
+ROUTE_AUTO, ROUTE_GREEN, ROUTE_PROJECTED = 0, 1, 2
+WS_COLD, WS_PREV, WS_TAYLOR, WS_LEARNED = 0, 1, 2, 3
+
+EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_precond_apply", "nm_pcg_solve",
+            "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream",
+            "nm_last_error", "nm_destroy")
+
+
+class NewmarkError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"newmark error {code}: {msg}")
+        self.code = code
+
+
+class _Problem(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("n_phases", C.c_int),
+                ("phase_id", C.c_void_p), ("C_voigt", C.c_void_p), ("rho", C.c_void_p),
+                ("gamma_idx", C.c_void_p), ("n_gamma", C.c_int64), ("u0", C.c_void_p), ("v0", C.c_void_p),
+                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double)]
+
+
+class _Options(C.Structure):
+    _fields_ = [("precision", C.c_int), ("route", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
+                ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("warm_start", C.c_int),
+                ("green_tol", C.c_double), ("compute_reaction", C.c_int), ("true_residual", C.c_int)]
+
+
+class StepStats(C.Structure):
+    _fields_ = [("iters", C.c_int * 2), ("sweeps", C.c_int), ("inner_iters", C.c_int), ("relres", C.c_double),
+                ("t_step_ms", C.c_double), ("t_warm_ms", C.c_double)]
+
+    def as_dict(self):
+        return {"iters": list(self.iters), "sweeps": self.sweeps, "inner_iters": self.inner_iters,
+                "relres": self.relres, "t_step_ms": self.t_step_ms, "t_warm_ms": self.t_warm_ms}
+
+
+_lib = None
+
+
+def load_library():
+    """Load the built HIP library; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libnewmark.so is not built (run __graft_entry__.build() or "
+                           "python paper_2211_08263_amd/build.py); there is no CPU fallback")
+    L = C.CDLL(LIB_PATH)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    L.nm_newmark_init.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), vp, C.POINTER(vp)]
+    L.nm_newmark_step.argtypes = [vp, vp, i, C.POINTER(StepStats)]
+    L.nm_apply_operator.argtypes = [vp, vp, vp, i]
+    L.nm_precond_apply.argtypes = [vp, vp, vp, i]
+    L.nm_pcg_solve.argtypes = [vp, vp, vp, i, d, i, i, C.POINTER(C.c_int), C.POINTER(C.c_double)]
+    L.nm_get_state.argtypes = [vp, vp, vp, vp, vp, C.POINTER(C.c_int64)]
+    L.nm_set_state.argtypes = [vp, vp, vp, vp, C.c_int64]
+    L.nm_state_device_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
+    L.nm_green_matrix.argtypes = [vp, vp]
+    L.nm_get_stream.argtypes = [vp]
+    L.nm_get_stream.restype = vp
+    L.nm_last_error.argtypes = [vp]
+    L.nm_last_error.restype = C.c_char_p
+    L.nm_destroy.argtypes = [vp]
+    L.nm_destroy.restype = None
+    _lib = L
+    return L
+
+
+@dataclass
+class Options:
+    precision: int = PREC_FP64
+    route: int = ROUTE_PROJECTED
+    tol: float = 1e-8
+    max_iter: int = 1000
+    inner_tol: float = 1e-4
+    max_sweeps: int = 20
+    warm_start: int = WS_PREV
+    green_tol: float = 0.0
+    compute_reaction: int = 0
+    true_residual: int = 0
+
+
+class Context:
+    """An initialised solver (nm_newmark_init); call close() or use as a context manager."""
+
+    def __init__(self, ptr, problem_arrays, dim, n, n_gamma):
+        self._ptr = ptr
+        self._keep = problem_arrays
+        self.dim = dim
+        self.n = n
+        self.N = n[0] * n[1] * n[2]
+        self.n_gamma = n_gamma
+
+    @property
+    def handle(self):
+        if not self._ptr:
+            raise RuntimeError("context is closed")
+        return self._ptr
+
+    def last_error(self) -> str:
+        return load_library().nm_last_error(self.handle).decode()
+
+    def check(self, code: int):
+        if code != NM_OK:
+            raise NewmarkError(code, self.last_error())
+
+    def close(self):
+        if self._ptr:
+            load_library().nm_destroy(self._ptr)
+            self._ptr = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voigt, rho, gamma_idx, dt: float,
+                 beta: float = 0.25, gamma_nm: float = 0.5, u0=None, v0=None, options: Optional[Options] = None,
+                 stream=None) -> Context:
+    lib = load_library()
+    nn = [int(x) for x in n] + [1] * (3 - len(n))
+    LL = [float(x) for x in L] + [1.0] * (3 - len(L))
+    ph = np.ascontiguousarray(phase_id, dtype=np.uint16).reshape(-1)
+    Cv = _c64(C_voigt).reshape(-1)
+    rh = _c64(rho).reshape(-1)
+    g = np.ascontiguousarray(gamma_idx, dtype=np.int64).reshape(-1)
+    u0a = None if u0 is None else _c64(u0).reshape(-1)
+    v0a = None if v0 is None else _c64(v0).reshape(-1)
+    pb = _Problem(int(dim), (C.c_int * 3)(*nn), (C.c_double * 3)(*LL), rh.size, ph.ctypes.data, Cv.ctypes.data,
+                  rh.ctypes.data, g.ctypes.data if g.size else None, g.size,
+                  None if u0a is None else u0a.ctypes.data, None if v0a is None else v0a.ctypes.data,
+                  float(dt), float(beta), float(gamma_nm))
+    o = options or Options()
+    op = _Options(o.precision, o.route, o.tol, o.max_iter, o.inner_tol, o.max_sweeps, o.warm_start, o.green_tol,
+                  o.compute_reaction, o.true_residual)
+    out = C.c_void_p()
+    code = lib.nm_newmark_init(C.byref(pb), C.byref(op), stream, C.byref(out))
+    ctx = Context(out.value, (ph, Cv, rh, g), int(dim), tuple(nn), int(g.size))
+    if code != NM_OK:
+        msg = ctx.last_error() if out.value else ""
+        ctx.close()
+        raise NewmarkError(code, msg)
+    return ctx
+
+
+def newmark_init_problem(pb, options: Optional[Options] = None, u0=None, v0=None, stream=None) -> Context:
+    """newmark_init from a workloads.Problem."""
+    return newmark_init(pb.dim, pb.n, pb.L, pb.phase_id, pb.C21, pb.rho, pb.gamma_idx, pb.dt, pb.beta, pb.gamma_nm,
+                        u0=u0, v0=v0, options=options, stream=stream)
+
+
+def newmark_step(ctx: Context, U, per_point: bool = False) -> dict:
+    Ua = _c64(U).reshape(-1)
+    st = StepStats()
+    ctx.check(load_library().nm_newmark_step(ctx.handle, Ua.ctypes.data, int(bool(per_point)), C.byref(st)))
+    return st.as_dict()
+
+
+def _dtype_code(t):
+    import torch
+    if t.dtype == torch.float64:
+        return NM_FP64
+    if t.dtype == torch.float32:
+        return NM_FP32
+    raise TypeError("float64 or float32 tensors expected")
+
+
+def _check_field(ctx, t):
+    if not t.is_cuda or not t.is_contiguous() or t.numel() != 3 * ctx.N:
+        raise ValueError("expected a contiguous device tensor of 3 x N values")
+
+
+def apply_operator(ctx: Context, u, out) -> None:
+    """out = A(u) on device tensors (3 x N, float64 or float32); asynchronous on the context stream."""
+    _check_field(ctx, u)
+    _check_field(ctx, out)
+    if u.dtype != out.dtype:
+        raise TypeError("u and out must share a dtype")
+    ctx.check(load_library().nm_apply_operator(ctx.handle, u.data_ptr(), out.data_ptr(), _dtype_code(u)))
+
+
+def precond_apply(ctx: Context, r, z) -> None:
+    _check_field(ctx, r)
+    _check_field(ctx, z)
+    if r.dtype != z.dtype:
+        raise TypeError("r and z must share a dtype")
+    ctx.check(load_library().nm_precond_apply(ctx.handle, r.data_ptr(), z.data_ptr(), _dtype_code(r)))
+
+
+def pcg_solve(ctx: Context, b, x, masked: bool = False, tol: float = 1e-10, max_iter: int = 1000,
+              fixed_iters: int = -1):
+    _check_field(ctx, b)
+    _check_field(ctx, x)
+    it = C.c_int(0)
+    rel = C.c_double(0)
+    ctx.check(load_library().nm_pcg_solve(ctx.handle, b.data_ptr(), x.data_ptr(), int(bool(masked)), float(tol),
+                                          int(max_iter), int(fixed_iters), C.byref(it), C.byref(rel)))
+    return it.value, rel.value
+
+
+def get_state(ctx: Context):
+    N, d = ctx.N, ctx.dim
+    u = np.empty(d * N)
+    v = np.empty(d * N)
+    a = np.empty(d * N)
+    F = np.empty(max(1, d * ctx.n_gamma))
+    step = C.c_int64(0)
+    ctx.check(load_library().nm_get_state(ctx.handle, u.ctypes.data, v.ctypes.data, a.ctypes.data, F.ctypes.data,
+                                          C.byref(step)))
+    shp = (d, ctx.n[2], ctx.n[1], ctx.n[0])
+    return {"u": u.reshape(shp), "v": v.reshape(shp), "a": a.reshape(shp), "F": F[: d * ctx.n_gamma],
+            "step": step.value}
+
+
+def set_state(ctx: Context, u, v, a, step: int) -> None:
+    ua, va, aa = _c64(u).reshape(-1), _c64(v).reshape(-1), _c64(a).reshape(-1)
+    ctx.check(load_library().nm_set_state(ctx.handle, ua.ctypes.data, va.ctypes.data, aa.ctypes.data, int(step)))
+
+
+def state_device_ptrs(ctx: Context):
+    u, v, a = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    ctx.check(load_library().nm_state_device_ptrs(ctx.handle, C.byref(u), C.byref(v), C.byref(a)))
+    return u.value, v.value, a.value
+
+
+def green_matrix(ctx: Context) -> np.ndarray:
+    nd = ctx.dim * ctx.n_gamma
+    G = np.empty((nd, nd))
+    ctx.check(load_library().nm_green_matrix(ctx.handle, G.ctypes.data))
+    return G
+
+
+def get_stream(ctx: Context) -> int:
+    return load_library().nm_get_stream(ctx.handle) or 0
