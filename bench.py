@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the implicit FFT Newmark solver on one MI355X.
+
+Workload: 256^3 Cu polycrystal (500 periodic Voronoi grains, random
+orientations), plane longitudinal Ricker pulse prescribed on the x = 0 voxel
+slab, Newmark beta = 1/4, gamma = 1/2, dt at CFL 2, PCG to a relative residual
+of 1e-8 (projected Gamma route, previous-step initial guess).
+
+A timed "step" is one full Newmark step: predictor and right-hand side,
+the constrained Krylov solve (every PCG iteration: one operator apply and one
+preconditioner apply), corrector.  Inputs are resident in HBM before timing.
+Prints one JSON line on stdout; progress goes to stderr.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "Newmark steps/s & operator GVoxel/s at 256^3; learned+mixed vs plain FP64"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+# Algorithmic HBM bytes per voxel of each pass of one operator apply, in units of
+# F = one real scalar field (8 B/voxel FP64, 4 B FP32; a half spectrum of one
+# component is the same size), plus the 2-byte grain id where a pass reads it.
+OPERATOR_PASS_FIELDS = {"x_fwd": 6, "y_fwd3": 6, "z_grad": 9, "y_inv6": 12, "x_stress": 12, "y_fwd6": 12,
+                        "z_div": 9, "y_inv3": 6, "x_inv_inertia": 9}
+OPERATOR_PASS_ID_BYTES = {"x_stress": 2, "x_inv_inertia": 2}
+
+
+def pass_bytes_per_voxel(name, real_bytes):
+    return OPERATOR_PASS_FIELDS[name] * real_bytes + OPERATOR_PASS_ID_BYTES.get(name, 0)
+
+
+def operator_bytes_per_voxel(real_bytes):
+    return sum(pass_bytes_per_voxel(k, real_bytes) for k in OPERATOR_PASS_FIELDS)
+
+
+def run_variant(pb, opts, steps, warmup, label):
+    import torch
+    from paper_2211_08263_amd import newmark as nmb
+    t0 = time.time()
+    ctx = nmb.newmark_init_problem(pb, opts)
+    log(f"[{label}] init {time.time() - t0:.1f}s")
+    stats = []
+    try:
+        for s in range(warmup):
+            nmb.newmark_step(ctx, pb.U(s + 1))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for s in range(warmup, warmup + steps):
+            stats.append(nmb.newmark_step(ctx, pb.U(s + 1)))
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    finally:
+        ctx.close()
+    its = [st["iters"][0] for st in stats]
+    inner = [st["inner_iters"] for st in stats]
+    sweeps = [st["sweeps"] for st in stats]
+    log(f"[{label}] {steps} steps in {dt:.3f}s -> {steps / dt:.3f} steps/s; iters {its} inner {inner}")
+    return {"steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "iters_per_step": its,
+            "inner_iters_per_step": inner, "sweeps_per_step": sweeps,
+            "relres_max": max(st["relres"] for st in stats)}
+
+
+def operator_rates(pb):
+    """Operator GVoxel/s (FP64 and FP32) with HIP events on the library's stream, and
+    per-pass event timings of the operator chain."""
+    import torch
+    from paper_2211_08263_amd import newmark as nmb
+    N = pb.n_vox
+    out = {}
+    ctx = nmb.newmark_init_problem(pb, nmb.Options())
+    try:
+        stream = torch.cuda.ExternalStream(nmb.get_stream(ctx))
+        g = torch.Generator(device="cuda").manual_seed(7)
+        for dt, label, rb in ((torch.float64, "fp64", 8), (torch.float32, "fp32", 4)):
+            u = torch.randn(3 * N, device="cuda", dtype=torch.float64, generator=g).to(dt)
+            Au = torch.empty_like(u)
+            torch.cuda.synchronize()
+            for _ in range(3):
+                nmb.apply_operator(ctx, u, Au)
+            times = []
+            for _ in range(20):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                nmb.apply_operator(ctx, u, Au)
+                e1.record(stream)
+                e1.synchronize()
+                times.append(e0.elapsed_time(e1))
+            times.sort()
+            med = times[len(times) // 2]
+            passes = nmb.profile_passes(ctx, 0, u, Au, reps=10)
+            pre = nmb.profile_passes(ctx, 1, u, Au, reps=10)
+            bpv = operator_bytes_per_voxel(rb)
+            out[label] = {"apply_ms_median": med, "gvoxel_per_s": N / (med * 1e-3) / 1e9,
+                          "model_bytes_per_voxel": bpv, "model_GBps": bpv * N / (med * 1e-3) / 1e9,
+                          "passes_ms": passes, "precond_passes_ms": pre}
+            log(f"[operator {label}] median {med:.3f} ms -> {N / med / 1e6:.2f} GVoxel/s, "
+                f"{bpv * N / med / 1e6:.0f} GB/s model; passes {passes}")
+    finally:
+        ctx.close()
+    return out
+
+
+def cpu_baseline(pb, iters_per_step):
+    """The FP64 oracle (single thread) timed on one operator apply of this workload."""
+    import numpy as np
+    import oracle
+    from paper_2211_08263_amd import workloads as W
+    op = oracle.OracleProblem.from_problem(pb)
+    u = W.random_field(op.field_shape, seed=7)
+    log("[cpu] oracle operator apply on the full grid ...")
+    t0 = time.perf_counter()
+    op.apply(u)
+    t_apply = time.perf_counter() - t0
+    applies = iters_per_step + 2  # PCG iterations + initial residual + reference norm
+    step_s = applies * t_apply
+    log(f"[cpu] one apply {t_apply:.1f}s -> >= {step_s:.0f}s per step")
+    return {"value": 1.0 / step_s, "unit": "steps/s", "cores": 1, "kind": "oracle",
+            "sample": (f"one FP64 oracle operator apply on the {pb.n[0]}^3 workload ({t_apply:.1f} s, 1 thread); "
+                       f"per-step time = {applies} applies (mean PCG iterations per FP64 GPU step + 2), "
+                       "preconditioner and vector work excluded, so this is an upper bound on the oracle rate"),
+            "apply_s": t_apply, "gvoxel_per_s": pb.n_vox / t_apply / 1e9}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=256)
+    ap.add_argument("--grains", type=int, default=500)
+    ap.add_argument("--seed", type=int, default=3)
+    ap.add_argument("--variants", default="fp64,mixed")
+    ap.add_argument("--cpu-sample", choices=["apply", "none"], default="apply")
+    ap.add_argument("--skip-operator", action="store_true")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (HBM counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the multi-GPU path is a design "
+              "note, not part of this build", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2211_08263_amd import newmark as nmb
+    from paper_2211_08263_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    if args.copy_probe_mib:
+        x = torch.empty(args.copy_probe_mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        y = torch.empty_like(x)
+        torch.cuda.synchronize()
+        y.copy_(x)
+        torch.cuda.synchronize()
+        del x, y
+    t0 = time.time()
+    pb = W.make_polycrystal(n=args.n, n_grains=args.grains, seed=args.seed)
+    log(f"[setup] polycrystal {args.n}^3 with {args.grains} grains in {time.time() - t0:.1f}s; "
+        f"dt {pb.dt:.4f}, fc {pb.pulse_fc:.4f}, |Gamma| {pb.gamma_idx.size}")
+
+    variants = {}
+    for v in args.variants.split(","):
+        if v == "fp64":
+            o = nmb.Options(tol=1e-8, max_iter=500, warm_start=nmb.WS_PREV)
+        elif v == "mixed":
+            o = nmb.Options(tol=1e-8, max_iter=500, warm_start=nmb.WS_PREV, precision=nmb.PREC_MIXED,
+                            inner_tol=1e-4)
+        else:
+            raise SystemExit(f"unknown variant {v}")
+        variants[v] = run_variant(pb, o, args.steps, args.warmup, v)
+
+    op = {} if args.skip_operator else operator_rates(pb)
+    head = "mixed" if "mixed" in variants else next(iter(variants))
+    hv = variants[head]
+    roof = None
+    if op:
+        passes = op["fp64"]["passes_ms"]
+        dom = max(passes, key=passes.get)
+        bpv = pass_bytes_per_voxel(dom, 8)
+        achieved = bpv * pb.n_vox / (passes[dom] * 1e-3) / 1e9
+        roof = {"bound": "hbm", "kernel": f"{dom} (fp64 operator pass)", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None, "bytes_per_voxel": bpv, "avg_ms": passes[dom],
+                "operator_chain_GBps_fp64": round(op["fp64"]["model_GBps"], 1),
+                "operator_chain_frac_fp64": round(op["fp64"]["model_GBps"] / HBM_PEAK_GBS, 4)}
+    cpu = None
+    if args.cpu_sample == "apply":
+        fp = variants.get("fp64", hv)
+        cpu = cpu_baseline(pb, int(round(float(np.mean(fp["iters_per_step"])))))
+    line = {
+        "metric": METRIC, "value": round(hv["steps_per_s"], 4), "unit": "steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(hv["ms_per_step"], 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f32+f64" if head == "mixed" else "f64", "data": "synthetic",
+        "config": {"workload": f"{args.n}^3 Cu polycrystal, {args.grains} Voronoi grains (seed {args.seed}), "
+                               "x=0 slab Ricker, tol 1e-8, projected Gamma route",
+                   "headline_variant": head, "grid": [args.n] * 3, "dt": pb.dt, "tol": 1e-8,
+                   "variants": variants,
+                   "operator": op},
+        "roofline": roof, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

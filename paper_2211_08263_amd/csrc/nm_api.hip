@@ -451,6 +451,59 @@ template <typename T> int precond_impl(nm_ctx* c, const T* r, T* z)
     return chain_precond<T>(c, XF_PLAIN, fa, ia);
 }
 
+// Event-timed passes of one operator (which == 0) or preconditioner (which == 1) apply.
+template <typename T> int profile_impl(nm_ctx* c, int which, const T* in, T* out, int reps, double* ms)
+{
+    hipStream_t s = c->stream;
+    void* spec = Prec<T>::spec(c);
+    const void* tw = Prec<T>::tw(c);
+    const int np = which == 0 ? 9 : 5;
+    hipEvent_t ev[10];
+    for (int i = 0; i <= np; i++) HIPCHK(c, hipEventCreate(&ev[i]));
+    std::vector<double> acc(np, 0.0);
+    XFwdArgs fa = xf_args(c, spec);
+    fa.src = in;
+    const uint8_t* nomask = nullptr;
+    XInvArgs ia = xi_args(c, spec, out, in, Prec<T>::rho(c), nomask, nullptr);
+    int rc = NM_OK;
+    for (int rep = 0; rep < reps && rc == NM_OK; rep++) {
+        int k = 0;
+        auto mark = [&]() { return hipEventRecord(ev[k++], s) == hipSuccess ? 0 : -2; };
+        rc = mark();
+        if (which == 0) {
+            rc |= launch_xfwd<T>(XF_PLAIN, c->n1, fa, tw, s) | mark();
+            rc |= launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
+            rc |= launch_zspec<T>(ZOP_GRAD, c->sp, c->NS, spec, tw, s) | mark();
+            rc |= launch_ypass<T>(+1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s) | mark();
+            rc |= launch_xstress<T>(c->n1, spec, (long)c->n2 * c->n3, c->NS, c->phase, Prec<T>::C(c), tw, s) | mark();
+            rc |= launch_ypass<T>(-1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s) | mark();
+            rc |= launch_zspec<T>(ZOP_DIV, c->sp, c->NS, spec, tw, s) | mark();
+            rc |= launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
+            rc |= launch_xinv<T>(XI_OPERATOR, c->n1, ia, tw, s) | mark();
+        } else {
+            rc |= launch_xfwd<T>(XF_PLAIN, c->n1, fa, tw, s) | mark();
+            rc |= launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
+            rc |= launch_zspec<T>(ZOP_PRECOND, c->sp, c->NS, spec, tw, s) | mark();
+            rc |= launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
+            rc |= launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s) | mark();
+        }
+        if (rc != 0) break;
+        if (hipEventSynchronize(ev[np]) != hipSuccess) {
+            rc = -2;
+            break;
+        }
+        for (int i = 0; i < np; i++) {
+            float t = 0;
+            (void)hipEventElapsedTime(&t, ev[i], ev[i + 1]);
+            acc[i] += t;
+        }
+    }
+    for (int i = 0; i <= np; i++) (void)hipEventDestroy(ev[i]);
+    if (rc != 0) return fail(c, NM_EHIP, "pass launch failed during profiling");
+    for (int i = 0; i < np; i++) ms[i] = acc[i] / reps;
+    return NM_OK;
+}
+
 } // namespace
 
 extern "C" {
@@ -830,6 +883,16 @@ int nm_state_device_ptrs(nm_ctx* c, void** u, void** v, void** a)
     if (v) *v = c->v;
     if (a) *a = c->a;
     return NM_OK;
+}
+
+int nm_profile_passes(nm_ctx* c, int which, const void* u_dev, void* out_dev, int dtype, int reps, double* ms)
+{
+    if (!c) return NM_EINVAL;
+    if (!u_dev || !out_dev || u_dev == out_dev || !ms || reps <= 0 || (which != 0 && which != 1))
+        return fail(c, NM_EINVAL, "bad arguments");
+    if (dtype == NM_FP64) return profile_impl<double>(c, which, (const double*)u_dev, (double*)out_dev, reps, ms);
+    if (dtype == NM_FP32) return profile_impl<float>(c, which, (const float*)u_dev, (float*)out_dev, reps, ms);
+    return fail(c, NM_EINVAL, "dtype must be NM_FP64 or NM_FP32");
 }
 
 void* nm_get_stream(nm_ctx* c) { return c ? (void*)c->stream : nullptr; }

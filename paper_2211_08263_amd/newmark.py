@@ -23,7 +23,7 @@ ROUTE_AUTO, ROUTE_GREEN, ROUTE_PROJECTED = 0, 1, 2
 WS_COLD, WS_PREV, WS_TAYLOR, WS_LEARNED = 0, 1, 2, 3
 
 EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_precond_apply", "nm_pcg_solve",
-            "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream",
+            "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream", "nm_profile_passes",
             "nm_last_error", "nm_destroy")
 
 
@@ -77,6 +77,7 @@ def load_library():
     L.nm_set_state.argtypes = [vp, vp, vp, vp, C.c_int64]
     L.nm_state_device_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
     L.nm_green_matrix.argtypes = [vp, vp]
+    L.nm_profile_passes.argtypes = [vp, i, vp, vp, i, i, C.POINTER(C.c_double)]
     L.nm_get_stream.argtypes = [vp]
     L.nm_get_stream.restype = vp
     L.nm_last_error.argtypes = [vp]
@@ -261,6 +262,21 @@ def green_matrix(ctx: Context) -> np.ndarray:
     G = np.empty((nd, nd))
     ctx.check(load_library().nm_green_matrix(ctx.handle, G.ctypes.data))
     return G
+
+
+OPERATOR_PASSES = ("x_fwd", "y_fwd3", "z_grad", "y_inv6", "x_stress", "y_fwd6", "z_div", "y_inv3", "x_inv_inertia")
+PRECOND_PASSES = ("x_fwd", "y_fwd3", "z_precond", "y_inv3", "x_inv")
+
+
+def profile_passes(ctx: Context, which: int, u, out, reps: int = 10):
+    """Average event-timed duration (ms) of every pass of one operator (0) or preconditioner (1) apply."""
+    _check_field(ctx, u)
+    _check_field(ctx, out)
+    ms = (C.c_double * 9)()
+    ctx.check(load_library().nm_profile_passes(ctx.handle, int(which), u.data_ptr(), out.data_ptr(),
+                                               _dtype_code(u), int(reps), ms))
+    names = OPERATOR_PASSES if which == 0 else PRECOND_PASSES
+    return {nm: ms[i] for i, nm in enumerate(names)}
 
 
 def get_stream(ctx: Context) -> int:
