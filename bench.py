@@ -32,8 +32,8 @@ def log(*a):
 # Algorithmic HBM bytes per voxel of each pass of one operator apply, in units of
 # F = one real scalar field (8 B/voxel FP64, 4 B FP32; a half spectrum of one
 # component is the same size), plus the 2-byte grain id where a pass reads it.
-OPERATOR_PASS_FIELDS = {"x_fwd": 6, "y_fwd3": 6, "z_grad": 9, "y_inv6": 12, "x_stress": 12, "y_fwd6": 12,
-                        "z_div": 9, "y_inv3": 6, "x_inv_inertia": 9}
+OPERATOR_PASS_FIELDS = {"x_fwd": 6, "y_deriv": 6, "z_strain": 12, "x_stress": 12, "y_div": 8, "z_div": 9,
+                        "x_inv_inertia": 9}
 OPERATOR_PASS_ID_BYTES = {"x_stress": 2, "x_inv_inertia": 2}
 
 

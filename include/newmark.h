@@ -140,7 +140,7 @@ int nm_state_device_ptrs(nm_ctx* ctx, void** u, void** v, void** a);
 /* The Green matrix (d*n_gamma)^2, row major, before factorization; GREEN route only. */
 int nm_green_matrix(const nm_ctx* ctx, double* G);
 
-/* Measurement: run the passes of one operator apply (which == 0: nine passes)
+/* Measurement: run the passes of one operator apply (which == 0: seven passes)
  * or one preconditioner apply (which == 1: five passes) reps times on the
  * context stream, with a HIP event pair around every pass; ms[i] receives the
  * average duration of pass i in chain order (ms needs 9 entries).  Buffers as

@@ -21,10 +21,19 @@
 
 using namespace nm;
 
+// Padding (complex elements) of the half-spectrum plane and component strides.
+#ifndef NM_PAD_PLANE
+#define NM_PAD_PLANE 0
+#endif
+#ifndef NM_PAD_COMP
+#define NM_PAD_COMP 0
+#endif
+
 struct nm_ctx {
     // problem
     int dim = 3, n1 = 0, n2 = 0, n3 = 0, nph = 0;
     long N = 0, NS = 0, ng = 0;
+    SpecLayout lay{};
     double dt = 0, beta = 0.25, gam = 0.5;
     std::vector<int64_t> gidx_h;
     nm_options opt{};
@@ -52,9 +61,11 @@ struct nm_ctx {
     double *u = nullptr, *v = nullptr, *a = nullptr, *ut = nullptr, *b = nullptr, *w = nullptr;
     double *r = nullptr, *z = nullptr, *p = nullptr, *q = nullptr, *uf = nullptr;
     double2* spec64 = nullptr;
+    double2* spec64b = nullptr;
     // FP32 fields
     float *d32 = nullptr, *rhs32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     float2* spec32 = nullptr;
+    float2* spec32b = nullptr;
     // Gamma buffers
     double* Ubuf = nullptr; // dim * max(ng, 1)
     double* gbuf = nullptr; // dim * max(ng, 1)
@@ -120,18 +131,21 @@ template <> struct Prec<double> {
     static const void* C(nm_ctx* c) { return c->C64; }
     static const void* rho(nm_ctx* c) { return c->rho64; }
     static void* spec(nm_ctx* c) { return c->spec64; }
+    static void* spec2(nm_ctx* c) { return c->spec64b; }
 };
 template <> struct Prec<float> {
     static const void* tw(nm_ctx* c) { return c->tw32; }
     static const void* C(nm_ctx* c) { return c->C32; }
     static const void* rho(nm_ctx* c) { return c->rho32; }
     static void* spec(nm_ctx* c) { return c->spec32; }
+    static void* spec2(nm_ctx* c) { return c->spec32b; }
 };
 
 XFwdArgs xf_args(nm_ctx* c, void* spec)
 {
     XFwdArgs a{};
     a.spec = spec;
+    a.lay = c->lay;
     a.scal = c->scal;
     a.nlines = 3L * c->n2 * c->n3;
     return a;
@@ -141,6 +155,7 @@ XInvArgs xi_args(nm_ctx* c, void* spec, void* out, const void* aux, const void* 
 {
     XInvArgs a{};
     a.spec = spec;
+    a.lay = c->lay;
     a.out = out;
     a.aux = aux;
     a.phase = c->phase;
@@ -153,20 +168,21 @@ XInvArgs xi_args(nm_ctx* c, void* spec, void* out, const void* aux, const void* 
     return a;
 }
 
-// q = A p as nine fused passes (see nm_passes.hip).
+// q = A p as seven passes: x-forward (3), D_y (3 -> 3), strain (6), x-inverse +
+// sigma = C : eps + x-forward (6), y part of the divergence, z part of the
+// divergence, x-inverse + rho p.  S and S2 are the two half-spectrum buffers.
 template <typename T> int chain_operator(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
 {
     hipStream_t s = c->stream;
     void* spec = Prec<T>::spec(c);
+    void* spec2 = Prec<T>::spec2(c);
     const void* tw = Prec<T>::tw(c);
     LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
-    LCHK(c, launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
-    LCHK(c, launch_zspec<T>(ZOP_GRAD, c->sp, c->NS, spec, tw, s));
-    LCHK(c, launch_ypass<T>(+1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s));
-    LCHK(c, launch_xstress<T>(c->n1, spec, (long)c->n2 * c->n3, c->NS, c->phase, Prec<T>::C(c), tw, s));
-    LCHK(c, launch_ypass<T>(-1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s));
-    LCHK(c, launch_zspec<T>(ZOP_DIV, c->sp, c->NS, spec, tw, s));
-    LCHK(c, launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
+    LCHK(c, launch_colop<T>(YOP_DERIV, c->sp, c->lay, spec, spec2, tw, s));
+    LCHK(c, launch_colop<T>(ZOP_STRAIN, c->sp, c->lay, spec, spec2, tw, s));
+    LCHK(c, launch_xstress<T>(c->n1, spec2, c->lay, c->phase, Prec<T>::C(c), tw, s));
+    LCHK(c, launch_colop<T>(YOP_DIV, c->sp, c->lay, spec, spec2, tw, s));
+    LCHK(c, launch_colop<T>(ZOP_DIVZ, c->sp, c->lay, spec, spec2, tw, s));
     LCHK(c, launch_xinv<T>(XI_OPERATOR, c->n1, ia, tw, s));
     return NM_OK;
 }
@@ -178,9 +194,9 @@ template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa
     void* spec = Prec<T>::spec(c);
     const void* tw = Prec<T>::tw(c);
     LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
-    LCHK(c, launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
-    LCHK(c, launch_zspec<T>(ZOP_PRECOND, c->sp, c->NS, spec, tw, s));
-    LCHK(c, launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s));
+    LCHK(c, launch_ypass<T>(-1, 3, c->lay, spec, tw, s));
+    LCHK(c, launch_zspec<T>(ZOP_PRECOND, c->sp, c->lay, spec, tw, s));
+    LCHK(c, launch_ypass<T>(+1, 3, c->lay, spec, tw, s));
     LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s));
     return NM_OK;
 }
@@ -457,7 +473,7 @@ template <typename T> int profile_impl(nm_ctx* c, int which, const T* in, T* out
     hipStream_t s = c->stream;
     void* spec = Prec<T>::spec(c);
     const void* tw = Prec<T>::tw(c);
-    const int np = which == 0 ? 9 : 5;
+    const int np = which == 0 ? 7 : 5;
     hipEvent_t ev[10];
     for (int i = 0; i <= np; i++) HIPCHK(c, hipEventCreate(&ev[i]));
     std::vector<double> acc(np, 0.0);
@@ -471,20 +487,19 @@ template <typename T> int profile_impl(nm_ctx* c, int which, const T* in, T* out
         auto mark = [&]() { return hipEventRecord(ev[k++], s) == hipSuccess ? 0 : -2; };
         rc = mark();
         if (which == 0) {
+            void* spec2 = Prec<T>::spec2(c);
             rc |= launch_xfwd<T>(XF_PLAIN, c->n1, fa, tw, s) | mark();
-            rc |= launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
-            rc |= launch_zspec<T>(ZOP_GRAD, c->sp, c->NS, spec, tw, s) | mark();
-            rc |= launch_ypass<T>(+1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s) | mark();
-            rc |= launch_xstress<T>(c->n1, spec, (long)c->n2 * c->n3, c->NS, c->phase, Prec<T>::C(c), tw, s) | mark();
-            rc |= launch_ypass<T>(-1, c->n1, c->n2, c->n3, 6, c->NS, spec, tw, s) | mark();
-            rc |= launch_zspec<T>(ZOP_DIV, c->sp, c->NS, spec, tw, s) | mark();
-            rc |= launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
+            rc |= launch_colop<T>(YOP_DERIV, c->sp, c->lay, spec, spec2, tw, s) | mark();
+            rc |= launch_colop<T>(ZOP_STRAIN, c->sp, c->lay, spec, spec2, tw, s) | mark();
+            rc |= launch_xstress<T>(c->n1, spec2, c->lay, c->phase, Prec<T>::C(c), tw, s) | mark();
+            rc |= launch_colop<T>(YOP_DIV, c->sp, c->lay, spec, spec2, tw, s) | mark();
+            rc |= launch_colop<T>(ZOP_DIVZ, c->sp, c->lay, spec, spec2, tw, s) | mark();
             rc |= launch_xinv<T>(XI_OPERATOR, c->n1, ia, tw, s) | mark();
         } else {
             rc |= launch_xfwd<T>(XF_PLAIN, c->n1, fa, tw, s) | mark();
-            rc |= launch_ypass<T>(-1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
-            rc |= launch_zspec<T>(ZOP_PRECOND, c->sp, c->NS, spec, tw, s) | mark();
-            rc |= launch_ypass<T>(+1, c->n1, c->n2, c->n3, 3, c->NS, spec, tw, s) | mark();
+            rc |= launch_ypass<T>(-1, 3, c->lay, spec, tw, s) | mark();
+            rc |= launch_zspec<T>(ZOP_PRECOND, c->sp, c->lay, spec, tw, s) | mark();
+            rc |= launch_ypass<T>(+1, 3, c->lay, spec, tw, s) | mark();
             rc |= launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s) | mark();
         }
         if (rc != 0) break;
@@ -535,6 +550,19 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
         return fail(c, NM_EUNSUPPORTED, "n3 must be 1 in 2D and a power of two in [8, 512] in 3D");
     c->N = (long)c->n1 * c->n2 * c->n3;
     c->NS = c->N / 2;
+    {
+        int l2 = 0;
+        while ((1 << l2) < c->n2) l2++;
+        c->lay.M = c->n1 / 2;
+        c->lay.n2 = c->n2;
+        c->lay.n3 = c->n3;
+        c->lay.log2n2 = l2;
+        // pad the plane and component strides of large spectra (power-of-two strides
+        // make the strided z pass collide in the memory system)
+        const long plane = (long)c->n2 * c->lay.M;
+        c->lay.ps = plane + (c->n3 > 1 && plane >= 4096 ? NM_PAD_PLANE : 0);
+        c->lay.cs = (long)c->n3 * c->lay.ps + (c->N >= (1L << 20) ? NM_PAD_COMP : 0);
+    }
     if (pb->n_phases < 1 || pb->n_phases > 65536) return fail(c, NM_EINVAL, "n_phases out of range");
     c->nph = pb->n_phases;
     if (!pb->phase_id || !pb->C_voigt || !pb->rho) return fail(c, NM_EINVAL, "null material arrays");
@@ -572,11 +600,17 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     c->sp.L1 = pb->L[0];
     c->sp.L2 = pb->L[1];
     c->sp.L3 = c->dim == 2 ? 1.0 : pb->L[2];
+    c->sp.k1 = 2.0 * M_PI / c->sp.L1;
+    c->sp.k2 = 2.0 * M_PI / c->sp.L2;
+    c->sp.k3 = 2.0 * M_PI / c->sp.L3;
     c->sp.n1 = c->n1;
     c->sp.n2 = c->n2;
     c->sp.n3 = c->n3;
     c->sp.dim = c->dim;
     c->sp.inv_ntot = 1.0 / (double)c->N;
+    c->sp.inv_n1 = 1.0 / c->n1;
+    c->sp.inv_n2 = 1.0 / c->n2;
+    c->sp.inv_n3 = 1.0 / c->n3;
     c->sp.bdt2 = c->beta * c->dt * c->dt;
     c->sp.rhobar = 0;
     for (int k = 0; k < 21; k++) c->sp.Cbar[k] = 0;
@@ -645,12 +679,14 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
         CHK(dalloc(c, f, n));
         LCHK(c, launch_fill<double>(*f, 0.0, n, s));
     }
-    CHK(dalloc(c, &c->spec64, 6 * c->NS));
+    CHK(dalloc(c, &c->spec64, 6 * c->lay.cs));
+    CHK(dalloc(c, &c->spec64b, 6 * c->lay.cs));
     if (c->route == NM_ROUTE_GREEN) {
         CHK(dalloc(c, &c->uf, n));
         LCHK(c, launch_fill<double>(c->uf, 0.0, n, s));
     }
-    CHK(dalloc(c, &c->spec32, 6 * c->NS));
+    CHK(dalloc(c, &c->spec32, 6 * c->lay.cs));
+    CHK(dalloc(c, &c->spec32b, 6 * c->lay.cs));
     if (c->opt.precision == NM_PREC_MIXED) {
         float** f32[] = {&c->d32, &c->rhs32, &c->r32, &c->z32, &c->p32, &c->q32};
         for (float** f : f32) {

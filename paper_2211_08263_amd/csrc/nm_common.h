@@ -38,6 +38,14 @@ __host__ __device__ __forceinline__ double freq_of(int k, int n, double L)
     return 6.283185307179586476925286766559 * (double)kk / L;
 }
 
+// Signed DFT index of bin k on an axis of n points (0 for the Nyquist bin and n == 1);
+// the frequency is this times 2 pi / L.
+__host__ __device__ __forceinline__ int freq_index(int k, int n)
+{
+    if (n == 1 || 2 * k == n) return 0;
+    return (2 * k < n) ? k : k - n;
+}
+
 constexpr int kBlock = 256;
 
 } // namespace nm

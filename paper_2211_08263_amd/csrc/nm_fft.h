@@ -108,16 +108,37 @@ template <int DIR, typename V> struct Dft<16, DIR, V> {
     }
 };
 
-// LDS address maps.  Padding of one element per R keeps the stride-R
-// writes of the first stages free of bank conflicts.
-template <int R> struct LineAddr {
+// LDS address maps.  Lines (one group of lanes per line, stride-1 reads and
+// stride-R writes in the first stages) use an XOR swizzle of the element index
+// inside aligned groups of 8 (16-byte elements) or 16 (8-byte elements), so
+// that both patterns spread over all banks without padding.
+template <int R, int ESIZE> struct LineAddr {
     int base;
-    __device__ __forceinline__ int operator()(int p) const { return base + p + p / R; }
+    __device__ __forceinline__ int operator()(int p) const
+    {
+        constexpr int S = ESIZE >= 16 ? 3 : 4, MASK = (1 << S) - 1;
+        return base + (p ^ ((p >> S) & MASK));
+    }
 };
 template <int R, int TX> struct ColAddr {
     int c;
     __device__ __forceinline__ int operator()(int p) const { return p * TX + c + p / R; }
 };
+
+// Synchronisation between the stages' LDS writes and reads.  A group that
+// lives inside one wavefront (x lines: G = L / R <= 64 lanes) only needs the
+// wave's LDS operations to stay in program order; columns spread over several
+// waves need a block barrier.
+template <bool WAVE> __device__ __forceinline__ void group_sync()
+{
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
 
 template <int L, int R> struct FftShape {
     static constexpr int G = L / R;
@@ -125,7 +146,7 @@ template <int L, int R> struct FftShape {
 };
 
 // One Stockham stage (radix chosen from Ns) followed by the remaining stages.
-template <int L, int R, int DIR, int Ns, typename V, typename Addr>
+template <int L, int R, int DIR, int Ns, bool WAVE, typename V, typename Addr>
 __device__ __forceinline__ void fft_stage(V (&v)[R], int t, V* lds, const Addr& addr, const V* __restrict__ tw)
 {
     if constexpr (Ns < L) {
@@ -137,7 +158,7 @@ __device__ __forceinline__ void fft_stage(V (&v)[R], int t, V* lds, const Addr& 
         if constexpr (!first) {
 #pragma unroll
             for (int m = 0; m < R; m++) v[m] = lds[addr(t + m * G)];
-            __syncthreads();
+            group_sync<WAVE>();
         }
 #pragma unroll
         for (int b = 0; b < NB; b++) {
@@ -164,19 +185,19 @@ __device__ __forceinline__ void fft_stage(V (&v)[R], int t, V* lds, const Addr& 
                 for (int r = 0; r < Rs; r++) lds[addr(base + r * Ns)] = a[r];
             }
         }
-        if constexpr (!last) __syncthreads();
-        fft_stage<L, R, DIR, Ns * Rs>(v, t, lds, addr, tw);
+        if constexpr (!last) group_sync<WAVE>();
+        fft_stage<L, R, DIR, Ns * Rs, WAVE>(v, t, lds, addr, tw);
     }
 }
 
 // Length-L transform of the group's sequence (see file comment).  tw points
 // at the table w_L^i = exp(-2 pi i i / L), i < L.  Every thread of the block
 // must call it (it contains block barriers); on exit the LDS area is free.
-template <int L, int R, int DIR, typename V, typename Addr>
+template <int L, int R, int DIR, bool WAVE = false, typename V, typename Addr>
 __device__ __forceinline__ void group_fft(V (&v)[R], int t, V* lds, const Addr& addr, const V* __restrict__ tw)
 {
-    // The last stage's LDS reads are followed by a barrier, so no trailing one is needed.
-    if constexpr (L > 1) fft_stage<L, R, DIR, 1>(v, t, lds, addr, tw);
+    // The last stage's LDS reads are followed by a sync, so no trailing one is needed.
+    if constexpr (L > 1) fft_stage<L, R, DIR, 1, WAVE>(v, t, lds, addr, tw);
 }
 
 // Offset of the table of length L (L = 2, 4, ..., 1024) inside the packed

@@ -8,12 +8,31 @@ namespace nm {
 // Spectral constants of the operator and of the reference-medium preconditioner.
 struct SpecParams {
     double L1, L2, L3;
+    double k1, k2, k3; // 2 pi / L_i
     int n1, n2, n3;
     int dim;          // 2 (plane strain, n3 == 1, z components held at zero) or 3
     double inv_ntot;  // 1 / (n1 n2 n3): normalization of one forward/inverse round trip
+    double inv_n1, inv_n2, inv_n3;
     double bdt2;      // beta dt^2
     double rhobar;    // volume-averaged density
     double Cbar[21];  // volume-averaged Voigt stiffness (upper triangle, row major)
+};
+
+// Layout of a half-spectrum buffer: element (c, kz, ky, kx) at
+// c * cs + kz * ps + ky * M + kx.  The plane and component strides may carry
+// padding so that the strided z pass does not hit power-of-two strides.
+struct SpecLayout {
+    int M;          // n1 / 2
+    int n2, n3;
+    int log2n2;
+    long ps;        // kz (plane) stride, >= n2 * M
+    long cs;        // component stride, >= n3 * ps
+    __host__ __device__ __forceinline__ long line(long l) const
+    {
+        // x line l = (component, kz, ky) in row-major order
+        const long yz = l % ((long)n2 * n3), c = l / ((long)n2 * n3);
+        return c * cs + (yz >> log2n2) * ps + (yz & (n2 - 1)) * (long)M;
+    }
 };
 
 // Fused stage in front of the x-direction real-to-complex transform.
@@ -22,6 +41,13 @@ enum XFwdMode { XF_PLAIN = 0, XF_PUPDATE = 1, XF_UPDATE = 2 };
 enum XInvMode { XI_PLAIN = 0, XI_OPERATOR = 1, XI_PRECOND = 2 };
 // Pointwise operator applied between the forward and inverse z transforms.
 enum ZOp { ZOP_GRAD = 0, ZOP_DIV = 1, ZOP_PRECOND = 2 };
+// Axis-wise derivative stages of the operator on x-spectral (kx, y, z) data:
+//   YOP_DERIV : S[3+j] = D_y S[j], j < 3
+//   ZOP_STRAIN: S2 = Voigt strain (eps11, eps22, eps33, g23, g13, g12) / n1 from
+//               U = S[0..2] and D_y U = S[3..5] (D_x = i xi1, D_z by a z round trip)
+//   YOP_DIV   : S[0..2] = (i xi1 s11 + D_y s12, i xi1 s12 + D_y s22, i xi1 s13 + D_y s23), sigma in S2
+//   ZOP_DIVZ  : S[j] = -beta dt^2 / n1 (S[j] + D_z sigma_j3)
+enum ColOp { YOP_DERIV = 0, YOP_DIV = 1, ZOP_STRAIN = 2, ZOP_DIVZ = 3 };
 
 // Device scalar block shared by the Krylov kernels (all double).
 enum ScalarSlot { S_ALPHA = 0, S_BETA = 1, S_FIRST = 2, S_RZ = 3, S_PQ = 4, S_RR = 5, S_COUNT = 8 };
@@ -35,11 +61,13 @@ struct XFwdArgs {
     const double* scal;   // device scalars
     double* partials;     // XF_UPDATE: per-block partial sums of r.r
     void* spec;           // output half spectrum
+    SpecLayout lay;
     long nlines;          // number of x lines (components x n2 x n3)
 };
 
 struct XInvArgs {
     const void* spec;     // input half spectrum
+    SpecLayout lay;
     void* out;            // output real field
     const void* aux;      // XI_OPERATOR: p ; XI_PRECOND: r
     const uint16_t* phase;
@@ -59,13 +87,17 @@ template <typename T> int launch_xfwd(int mode, int n1, const XFwdArgs& a, const
 template <typename T> int launch_xinv(int mode, int n1, const XInvArgs& a, const void* tw, hipStream_t s);
 // In-place x-inverse, Voigt stress sigma = C_g : eps, x-forward on 6 components.
 template <typename T>
-int launch_xstress(int n1, void* spec, long lines_per_comp, long NS, const uint16_t* phase, const void* C21,
-                   const void* tw, hipStream_t s);
+int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* phase, const void* C21, const void* tw,
+                   hipStream_t s);
 // In-place transform of ncomp components along y (dir -1 forward, +1 inverse).
 template <typename T>
-int launch_ypass(int dir, int n1, int n2, int n3, int ncomp, long NS, void* spec, const void* tw, hipStream_t s);
+int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s);
+// Axis-wise derivative stages of the operator (ColOp); S and S2 are two 6-component spectra.
+template <typename T>
+int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, void* S2, const void* tw,
+                 hipStream_t s);
 // In-place z-forward, pointwise operator, z-inverse.
 template <typename T>
-int launch_zspec(int op, const SpecParams& sp, long NS, void* spec, const void* tw, hipStream_t s);
+int launch_zspec(int op, const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s);
 
 } // namespace nm

@@ -73,6 +73,15 @@ template <typename V> __device__ __forceinline__ V c2r_pre(int k, V xk, V xm, V 
     return V{a.x - wb.y, a.y + wb.x};
 }
 
+// Copy the twiddle table of length L into LDS (block-cooperative; the caller
+// synchronizes the block before use).
+template <int L, typename V> __device__ __forceinline__ void stage_twiddles(V* dst, const V* __restrict__ tw)
+{
+    if constexpr (L >= 2) {
+        for (int i = threadIdx.x; i < L; i += blockDim.x) dst[i] = tw[tw_offset(L) + i];
+    }
+}
+
 // ---------------------------------------------------------------------------
 // x direction: real lines of N1 points, M = N1/2 complex points per line
 // ---------------------------------------------------------------------------
@@ -80,8 +89,15 @@ template <typename T, int N1, int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __restrict__ tw)
 {
     using V = cx_t<T>;
-    constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M + M / R;
+    constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M;
+    static_assert(G <= 64, "an x line must live inside one wavefront");
     __shared__ V lds[LPB * LP];
+    __shared__ V twsm[M + N1];
+    stage_twiddles<M>(twsm, tw);
+    stage_twiddles<N1>(twsm + M, tw);
+    __syncthreads();
+    const V* twM = twsm;
+    const V* twN = twsm + M;
     const int tid = threadIdx.x, ll = tid / G, t = tid % G;
     const long line = (long)blockIdx.x * LPB + ll;
     const bool valid = line < a.nlines;
@@ -131,17 +147,16 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
             }
         }
     }
-    LineAddr<R> addr{ll * LP};
-    group_fft<M, R, -1>(v, t, lds, addr, tw + tw_offset(M));
+    LineAddr<R, (int)sizeof(V)> addr{ll * LP};
+    group_fft<M, R, -1, true>(v, t, lds, addr, twM);
 #pragma unroll
     for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
-    __syncthreads();
+    group_sync<true>();
     V mir[R];
 #pragma unroll
     for (int m = 0; m < R; m++) mir[m] = lds[addr((M - (t + m * G)) & (M - 1))];
-    const V* twN = tw + tw_offset(N1);
     if (valid) {
-        V* out = (V*)a.spec + off;
+        V* out = (V*)a.spec + a.lay.line(line);
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int k = t + m * G;
@@ -158,28 +173,50 @@ template <typename T, int N1, int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __restrict__ tw)
 {
     using V = cx_t<T>;
-    constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M + M / R;
+    constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M;
+    static_assert(G <= 64, "an x line must live inside one wavefront");
     __shared__ V lds[LPB * LP];
+    __shared__ V twsm[M + N1];
+    stage_twiddles<M>(twsm, tw);
+    stage_twiddles<N1>(twsm + M, tw);
+    __syncthreads();
+    const V* twM = twsm;
+    const V* twN = twsm + M;
     const int tid = threadIdx.x, ll = tid / G, t = tid % G;
     const long line = (long)blockIdx.x * LPB + ll;
     const bool valid = line < a.nlines;
     const long off = line * M;
     V v[R];
+    const long soff = a.lay.line(line);
 #pragma unroll
-    for (int m = 0; m < R; m++) v[m] = valid ? ((const V*)a.spec)[off + t + m * G] : V{0, 0};
-    LineAddr<R> addr{ll * LP};
+    for (int m = 0; m < R; m++) v[m] = valid ? ((const V*)a.spec)[soff + t + m * G] : V{0, 0};
+    // the real-space operands of the fused stage are fetched before the transform
+    V au[R];
+    uint32_t ph[R];
+    uint16_t mk[R];
+    const long vline = line % a.lines_per_comp;
+    if constexpr (MODE != XI_PLAIN) {
+        const V* aux = (const V*)a.aux + off;
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int n = t + m * G;
+            au[m] = valid ? aux[n] : V{0, 0};
+            ph[m] = (valid && MODE == XI_OPERATOR) ? ((const uint32_t*)a.phase)[vline * M + n] : 0u;
+            mk[m] = (valid && a.mask) ? ((const uint16_t*)a.mask)[vline * M + n] : (uint16_t)0;
+        }
+    }
+    LineAddr<R, (int)sizeof(V)> addr{ll * LP};
 #pragma unroll
     for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
-    __syncthreads();
-    const V* twN = tw + tw_offset(N1);
+    group_sync<true>();
 #pragma unroll
     for (int m = 0; m < R; m++) {
         const int k = t + m * G;
         V xm = lds[addr((M - k) & (M - 1))];
         v[m] = c2r_pre(k, v[m], xm, twN[k]);
     }
-    __syncthreads();
-    group_fft<M, R, +1>(v, t, lds, addr, tw + tw_offset(M));
+    group_sync<true>();
+    group_fft<M, R, +1, true>(v, t, lds, addr, twM);
     double part = 0.0;
     if (valid) {
         V* out = (V*)a.out + off;
@@ -187,29 +224,20 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
 #pragma unroll
             for (int m = 0; m < R; m++) out[t + m * G] = v[m];
         } else {
-            const V* aux = (const V*)a.aux + off;
-            const long vline = line % a.lines_per_comp;
             const bool zero_comp = (a.dim == 2) && (line / a.lines_per_comp == 2);
-            const uint32_t* ph2 = (const uint32_t*)a.phase + vline * M;
-            const uint16_t* mk2 = a.mask ? (const uint16_t*)a.mask + vline * M : nullptr;
             const T* rho = (const T*)a.rho;
 #pragma unroll
             for (int m = 0; m < R; m++) {
                 const int n = t + m * G;
-                V au = aux[n];
                 V o = v[m];
                 if constexpr (MODE == XI_OPERATOR) {
-                    const uint32_t ph = ph2[n];
-                    o.x += rho[ph & 0xffffu] * au.x;
-                    o.y += rho[ph >> 16] * au.y;
+                    o.x += rho[ph[m] & 0xffffu] * au[m].x;
+                    o.y += rho[ph[m] >> 16] * au[m].y;
                 }
-                if (mk2) {
-                    const uint16_t mm = mk2[n];
-                    if (mm & 0x00ffu) o.x = 0;
-                    if (mm & 0xff00u) o.y = 0;
-                }
+                if (mk[m] & 0x00ffu) o.x = 0;
+                if (mk[m] & 0xff00u) o.y = 0;
                 if (zero_comp) o = V{0, 0};
-                part += (double)au.x * (double)o.x + (double)au.y * (double)o.y;
+                part += (double)au[m].x * (double)o.x + (double)au[m].y * (double)o.y;
                 out[n] = o;
             }
         }
@@ -233,19 +261,24 @@ template <typename T> __device__ __forceinline__ void voigt_stress(const T* __re
 }
 
 template <typename T, int N1, int R>
-__global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, long lpc, long NS, const uint16_t* __restrict__ phase,
+__global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout lay, const uint16_t* __restrict__ phase,
                                                     const T* __restrict__ C21, const cx_t<T>* __restrict__ tw)
 {
     using V = cx_t<T>;
-    constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M + M / R;
+    constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M;
+    static_assert(G <= 64, "an x line must live inside one wavefront");
     __shared__ V lds[LPB * LP];
+    __shared__ V twsm[M + N1];
+    stage_twiddles<M>(twsm, tw);
+    stage_twiddles<N1>(twsm + M, tw);
+    __syncthreads();
+    const V* twM = twsm;
+    const V* twN = twsm + M;
     const int tid = threadIdx.x, ll = tid / G, t = tid % G;
     const long line = (long)blockIdx.x * LPB + ll;
-    const bool valid = line < lpc;
-    const long off = line * M;
-    LineAddr<R> addr{ll * LP};
-    const V* twN = tw + tw_offset(N1);
-    const V* twM = tw + tw_offset(M);
+    const bool valid = line < (long)lay.n2 * lay.n3;
+    const long off = lay.line(line), NS = lay.cs;
+    LineAddr<R, (int)sizeof(V)> addr{ll * LP};
     T e[6][2 * R];
 #pragma unroll
     for (int c = 0; c < 6; c++) {
@@ -254,14 +287,14 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, long lpc, lon
         for (int m = 0; m < R; m++) v[m] = valid ? spec[c * NS + off + t + m * G] : V{0, 0};
 #pragma unroll
         for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
-        __syncthreads();
+        group_sync<true>();
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int k = t + m * G;
             v[m] = c2r_pre(k, v[m], lds[addr((M - k) & (M - 1))], twN[k]);
         }
-        __syncthreads();
-        group_fft<M, R, +1>(v, t, lds, addr, twM);
+        group_sync<true>();
+        group_fft<M, R, +1, true>(v, t, lds, addr, twM);
 #pragma unroll
         for (int m = 0; m < R; m++) {
             e[c][2 * m] = v[m].x;
@@ -275,11 +308,11 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, long lpc, lon
             const uint32_t ph = ph2[t + m * G];
 #pragma unroll
             for (int h = 0; h < 2; h++) {
-                const T* c = C21 + 21 * (h ? (ph >> 16) : (ph & 0xffffu));
+                const T* cg = C21 + 21 * (h ? (ph >> 16) : (ph & 0xffffu));
                 T ee[6], ss[6];
 #pragma unroll
                 for (int q = 0; q < 6; q++) ee[q] = e[q][2 * m + h];
-                voigt_stress(c, ee, ss);
+                voigt_stress(cg, ee, ss);
 #pragma unroll
                 for (int q = 0; q < 6; q++) e[q][2 * m + h] = ss[q];
             }
@@ -290,14 +323,14 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, long lpc, lon
         V v[R];
 #pragma unroll
         for (int m = 0; m < R; m++) v[m] = V{e[c][2 * m], e[c][2 * m + 1]};
-        group_fft<M, R, -1>(v, t, lds, addr, twM);
+        group_fft<M, R, -1, true>(v, t, lds, addr, twM);
 #pragma unroll
         for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
-        __syncthreads();
+        group_sync<true>();
         V mir[R];
 #pragma unroll
         for (int m = 0; m < R; m++) mir[m] = lds[addr((M - (t + m * G)) & (M - 1))];
-        __syncthreads();
+        group_sync<true>();
         if (valid) {
 #pragma unroll
             for (int m = 0; m < R; m++) {
@@ -311,25 +344,33 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, long lpc, lon
 // ---------------------------------------------------------------------------
 // y and z directions: tiles of TX consecutive kx columns, L points each.
 // ---------------------------------------------------------------------------
-template <int R> struct ColAddrRT {
+// Column tiles: element p of column c at p * TX + c.  With TX >= 8 complex
+// (16-byte elements) each group of 8 consecutive lanes covers all banks, so no
+// padding is needed; a compile-time TX (TXC > 0) lets the offsets fold into
+// the LDS instructions' immediate fields.  TXC == 0: runtime TX (small grids).
+template <int TXC> struct ColAddrT {
     int c, tx;
-    __device__ __forceinline__ int operator()(int p) const { return p * tx + c + p / R; }
+    __device__ __forceinline__ int operator()(int p) const { return p * (TXC > 0 ? TXC : tx) + c; }
 };
 
-template <typename T, int L, int R, int DIR>
-__global__ __launch_bounds__(kBlock) void k_ypass(cx_t<T>* data, long colstride, long planestride, long NS, int TX,
-                                                  const cx_t<T>* __restrict__ tw)
+template <typename T, int L, int R, int DIR, int BLK, int TXC>
+__global__ __launch_bounds__(BLK) void k_ypass(cx_t<T>* __restrict__ data, long colstride, long planestride, long cs,
+                                               int TXr, const cx_t<T>* __restrict__ tw)
 {
     using V = cx_t<T>;
     constexpr int G = L / R;
-    __shared__ V lds[kBlock * R + L / R + 1]; // TX * L <= 256 R, plus one pad per R rows
+    const int TX = TXC > 0 ? TXC : TXr;
+    __shared__ V lds[BLK * R]; // TX * L <= BLK R
+    __shared__ V twsm[L];
+    stage_twiddles<L>(twsm, tw);
+    __syncthreads();
     const int tid = threadIdx.x, c = tid % TX, t = tid / TX;
-    V* col = data + blockIdx.z * NS + blockIdx.y * planestride + (long)blockIdx.x * TX + c;
+    V* col = data + blockIdx.z * cs + blockIdx.y * planestride + (long)blockIdx.x * TX + c;
     V v[R];
 #pragma unroll
     for (int m = 0; m < R; m++) v[m] = col[(long)(t + m * G) * colstride];
-    ColAddrRT<R> addr{c, TX};
-    group_fft<L, R, DIR>(v, t, lds, addr, tw + tw_offset(L));
+    ColAddrT<TXC> addr{c, TX};
+    group_fft<L, R, DIR>(v, t, lds, addr, twsm);
 #pragma unroll
     for (int m = 0; m < R; m++) col[(long)(t + m * G) * colstride] = v[m];
 }
@@ -341,25 +382,28 @@ template <typename T> struct ZOps {
     static __device__ __forceinline__ V iscale(V a, T s) { return V{-a.y * s, a.x * s}; }
 };
 
-template <typename T, int L, int R, int OP>
-__global__ __launch_bounds__(kBlock) void k_zspec(cx_t<T>* data, long NS, int TX, SpecParams sp,
-                                                  const cx_t<T>* __restrict__ tw)
+template <typename T, int L, int R, int OP, int BLK, int TXC>
+__global__ __launch_bounds__(BLK) void k_zspec(cx_t<T>* __restrict__ data, long NS, long colstride, int TXr,
+                                               SpecParams sp, const cx_t<T>* __restrict__ tw)
 {
     using V = cx_t<T>;
     constexpr int G = L / R;
-    __shared__ V lds[kBlock * R + L / R + 1]; // TX * L <= 256 R, plus one pad per R rows
+    const int TX = TXC > 0 ? TXC : TXr;
+    __shared__ V lds[BLK * R]; // TX * L <= BLK R
+    __shared__ V twsm[L > 1 ? L : 2];
+    stage_twiddles<L>(twsm, tw);
+    __syncthreads();
     const int tid = threadIdx.x, c = tid % TX, t = tid / TX;
     const int M = sp.n1 / 2;
     const int kx = blockIdx.x * TX + c, ky = blockIdx.y;
-    const long colstride = (long)sp.n2 * M;
     V* col = data + (long)ky * M + kx;
-    ColAddrRT<R> addr{c, TX};
-    const V* twL = tw + tw_offset(L > 1 ? L : 2);
-    const T xi1 = (T)(6.283185307179586476925286766559 * kx / sp.L1);
-    const T xi2 = (T)freq_of(ky, sp.n2, sp.L2);
+    ColAddrT<TXC> addr{c, TX};
+    const V* twL = twsm;
+    const T xi1 = (T)(sp.k1 * kx);
+    const T xi2 = (T)(sp.k2 * freq_index(ky, sp.n2));
     T xi3[R];
 #pragma unroll
-    for (int m = 0; m < R; m++) xi3[m] = (T)freq_of(t + m * G, sp.n3, sp.L3);
+    for (int m = 0; m < R; m++) xi3[m] = (T)(sp.k3 * freq_index(t + m * G, sp.n3));
 
     if constexpr (OP == ZOP_GRAD || OP == ZOP_PRECOND) {
         V u[3][R];
@@ -507,12 +551,143 @@ __global__ __launch_bounds__(kBlock) void k_zspec(cx_t<T>* data, long NS, int TX
     }
 }
 
+
+// ---------------------------------------------------------------------------
+// Axis-wise derivative stages of the operator (see ColOp).  Data are x-spectral
+// and real in y and z, so D_x is the multiplier i xi1 and D_y, D_z are round
+// trips along one axis: forward FFT, i xi / n, inverse FFT.  Every element is
+// read and written by the thread that owns its row in the FFT register layout.
+// ---------------------------------------------------------------------------
+template <typename T, int L, int R, int OP, int BLK, int TXC>
+__global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>* __restrict__ S2, long rowstride,
+                                               long cs, int TXr, SpecParams sp, const cx_t<T>* __restrict__ tw)
+{
+    using V = cx_t<T>;
+    constexpr int G = L / R;
+    constexpr bool YAX = (OP == YOP_DERIV || OP == YOP_DIV);
+    const int TX = TXC > 0 ? TXC : TXr;
+    __shared__ V lds[BLK * R];
+    __shared__ V twsm[L > 1 ? L : 2];
+    stage_twiddles<L>(twsm, tw);
+    __syncthreads();
+    const int tid = threadIdx.x, c = tid % TX, t = tid / TX;
+    const int M = sp.n1 / 2;
+    const int kx = blockIdx.x * TX + c;
+    // y stages: block = (kx tile, z plane), rows along y at stride M;
+    // z stages: block = (kx tile, y row), rows along z at the plane stride.
+    // rowstride is the plane (kz) stride of the layout
+    const long start = YAX ? (long)blockIdx.y * rowstride : (long)blockIdx.y * M;
+    const long step = YAX ? (long)M : rowstride;
+    V* s1 = S + start + kx;
+    V* s2 = S2 + start + kx;
+    ColAddrT<TXC> addr{c, TX};
+    const V* twL = twsm;
+    const T xi1 = (T)(sp.k1 * kx);
+    const int n = YAX ? sp.n2 : sp.n3;
+    const double kax = YAX ? sp.k2 * sp.inv_n2 : sp.k3 * sp.inv_n3;
+    T mul[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) mul[m] = (T)(kax * freq_index(t + m * G, n));
+    auto ld = [&](const V* col, int comp, V (&v)[R]) {
+#pragma unroll
+        for (int m = 0; m < R; m++) v[m] = col[comp * cs + (long)(t + m * G) * step];
+    };
+    auto st = [&](V* col, int comp, const V (&v)[R]) {
+#pragma unroll
+        for (int m = 0; m < R; m++) col[comp * cs + (long)(t + m * G) * step] = v[m];
+    };
+    // v <- D v along the column (forward FFT, i xi / n, inverse FFT)
+    auto deriv = [&](V (&v)[R]) {
+        group_fft<L, R, -1>(v, t, lds, addr, twL);
+#pragma unroll
+        for (int m = 0; m < R; m++) v[m] = ZOps<T>::iscale(v[m], mul[m]);
+        group_fft<L, R, +1>(v, t, lds, addr, twL);
+    };
+    if constexpr (OP == YOP_DERIV) {
+#pragma unroll 1
+        for (int j = 0; j < 3; j++) {
+            V v[R];
+            ld(s1, j, v);
+            deriv(v);
+            st(s1, 3 + j, v);
+        }
+    } else if constexpr (OP == YOP_DIV) {
+        // (source of D_y, source of i xi1, output): sigma Voigt 0..5 = s11 s22 s33 s23 s13 s12
+        constexpr int SRC[3] = {5, 1, 3}, PT[3] = {0, 5, 4};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            V v[R], w[R];
+            ld(s2, SRC[j], v);
+            deriv(v);
+            ld(s2, PT[j], w);
+#pragma unroll
+            for (int m = 0; m < R; m++) v[m] = cadd(v[m], ZOps<T>::iscale(w[m], xi1));
+            st(s1, j, v);
+        }
+    } else if constexpr (OP == ZOP_STRAIN) {
+        const T sc = (T)sp.inv_n1;
+        V a[R], b[R];
+        // eps11 = i xi1 U1 ; A = D_z U1
+        ld(s1, 0, a);
+#pragma unroll
+        for (int m = 0; m < R; m++) b[m] = cscale(ZOps<T>::iscale(a[m], xi1), sc);
+        st(s2, 0, b);
+        deriv(a);
+        // g13 = D_z U1 + i xi1 U3 ; eps33 = D_z U3
+        ld(s1, 2, b);
+#pragma unroll
+        for (int m = 0; m < R; m++) a[m] = cscale(cadd(a[m], ZOps<T>::iscale(b[m], xi1)), sc);
+        st(s2, 4, a);
+        deriv(b);
+#pragma unroll
+        for (int m = 0; m < R; m++) b[m] = cscale(b[m], sc);
+        st(s2, 2, b);
+        // g23 = D_z U2 + D_y U3 ; g12 = D_y U1 + i xi1 U2 ; eps22 = D_y U2
+        ld(s1, 1, a);
+#pragma unroll
+        for (int m = 0; m < R; m++) b[m] = a[m];
+        deriv(b);
+        {
+            V d[R];
+            ld(s1, 5, d);
+#pragma unroll
+            for (int m = 0; m < R; m++) d[m] = cscale(cadd(b[m], d[m]), sc);
+            st(s2, 3, d);
+            ld(s1, 3, d);
+#pragma unroll
+            for (int m = 0; m < R; m++) d[m] = cscale(cadd(d[m], ZOps<T>::iscale(a[m], xi1)), sc);
+            st(s2, 5, d);
+            ld(s1, 4, d);
+#pragma unroll
+            for (int m = 0; m < R; m++) d[m] = cscale(d[m], sc);
+            st(s2, 1, d);
+        }
+    } else {
+        // q_j = -beta dt^2 / n1 (Q_j + D_z sigma_j3): sigma_13 = S2[4], sigma_23 = S2[3], sigma_33 = S2[2]
+        const T cd = (T)(-sp.bdt2 * sp.inv_n1);
+        constexpr int SRC[3] = {4, 3, 2};
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            V v[R], w[R];
+            ld(s2, SRC[j], v);
+            deriv(v);
+            ld(s1, j, w);
+#pragma unroll
+            for (int m = 0; m < R; m++) v[m] = cscale(cadd(v[m], w[m]), cd);
+            st(s1, j, v);
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Launchers
 // ---------------------------------------------------------------------------
 static inline int radix_x(int M) { return M >= 8 ? 8 : M; }
-static inline int radix_stress(int M, bool dbl) { return dbl ? (M >= 4 ? 4 : M) : (M >= 8 ? 8 : M); }
-static inline int radix_col(int L) { return L >= 8 ? 8 : L; }
+
+// Radix of the x-direction stress pass in FP64 (it holds six components per thread).
+#ifndef NM_STRESS_R64
+#define NM_STRESS_R64 4
+#endif
 
 int xfwd_blocks(int n1, long nlines)
 {
@@ -562,72 +737,159 @@ template <typename T> int launch_xinv(int mode, int n1, const XInvArgs& a, const
 }
 
 template <typename T>
-int launch_xstress(int n1, void* spec, long lpc, long NS, const uint16_t* phase, const void* C21, const void* tw,
+int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* phase, const void* C21, const void* tw,
                    hipStream_t s)
 {
+    const long lpc = (long)lay.n2 * lay.n3;
     const cx_t<T>* t = (const cx_t<T>*)tw;
     NM_SIZE_SWITCH(n1, {
         constexpr int M = NN / 2;
-        constexpr int R = sizeof(T) == 8 ? (M >= 4 ? 4 : M) : (M >= 8 ? 8 : M);
+        constexpr int R = sizeof(T) == 8 ? (M >= NM_STRESS_R64 ? NM_STRESS_R64 : M) : (M >= 8 ? 8 : M);
         constexpr int G = M / R, LPB = kBlock / G;
         const int blocks = (int)((lpc + LPB - 1) / LPB);
-        hipLaunchKernelGGL((k_xstress<T, NN, R>), dim3(blocks), dim3(kBlock), 0, s, (cx_t<T>*)spec, lpc, NS, phase,
+        hipLaunchKernelGGL((k_xstress<T, NN, R>), dim3(blocks), dim3(kBlock), 0, s, (cx_t<T>*)spec, lay, phase,
                            (const T*)C21, t);
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-// TX: columns per tile so that TX * (L / R) <= 256 and TX divides M.
-static inline int col_tile(int L, int M)
+// Radix and block size of the column passes.  The y pass holds one component
+// per thread (radix 16: one LDS exchange for L = 256); the fused z kernels hold
+// three components, so FP64 uses a smaller radix to bound register pressure.
+#ifndef NM_ZSPEC_R64
+#define NM_ZSPEC_R64 8
+#endif
+#ifndef NM_ZSPEC_BLK64
+#define NM_ZSPEC_BLK64 256
+#endif
+
+template <int L> constexpr int ypass_radix() { return L >= 16 ? 16 : L; }
+template <typename T, int L> constexpr int zspec_radix()
 {
-    const int G = L / radix_col(L);
-    int tx = kBlock / G;
-    return tx < M ? tx : M;
+    return L < 8 ? L : (sizeof(T) == 8 ? (NM_ZSPEC_R64 < L ? NM_ZSPEC_R64 : L) : (L >= 16 ? 16 : L));
 }
+template <typename T> constexpr int zspec_block() { return sizeof(T) == 8 ? NM_ZSPEC_BLK64 : 256; }
+
 
 template <typename T>
-int launch_ypass(int dir, int n1, int n2, int n3, int ncomp, long NS, void* spec, const void* tw, hipStream_t s)
+int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s)
 {
-    const int M = n1 / 2;
-    const int TX = col_tile(n2, M);
+    const int M = lay.M, n3 = lay.n3;
     const cx_t<T>* t = (const cx_t<T>*)tw;
-    NM_SIZE_SWITCH(n2, {
-        constexpr int R = NN >= 8 ? 8 : NN;
+    NM_SIZE_SWITCH(lay.n2, {
+        constexpr int R = ypass_radix<NN>();
         constexpr int G = NN / R;
+        constexpr int TXP = 256 / G;
+        const int TX = M >= TXP ? TXP : M;
         dim3 grid(M / TX, n3, ncomp), block(TX * G);
-        if (dir < 0)
-            hipLaunchKernelGGL((k_ypass<T, NN, R, -1>), grid, block, 0, s, (cx_t<T>*)spec, (long)M, (long)n2 * M, NS,
-                               TX, t);
-        else
-            hipLaunchKernelGGL((k_ypass<T, NN, R, +1>), grid, block, 0, s, (cx_t<T>*)spec, (long)M, (long)n2 * M, NS,
-                               TX, t);
+        cx_t<T>* d = (cx_t<T>*)spec;
+        if (M >= TXP) {
+            if (dir < 0)
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+            else
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+        } else {
+            if (dir < 0)
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+            else
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+        }
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-template <typename T, int L>
-static void zspec_dispatch(int op, dim3 grid, dim3 block, hipStream_t s, cx_t<T>* spec, long NS, int TX,
-                           const SpecParams& sp, const cx_t<T>* t)
+template <typename T, int L, int BLK, int TXC>
+static void zspec_dispatch(int op, dim3 grid, dim3 block, hipStream_t s, cx_t<T>* spec, const SpecLayout& lay,
+                           int TX, const SpecParams& sp, const cx_t<T>* t)
 {
-    constexpr int R = L >= 8 ? 8 : L;
-    if (op == ZOP_GRAD) hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_GRAD>), grid, block, 0, s, spec, NS, TX, sp, t);
-    else if (op == ZOP_DIV) hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_DIV>), grid, block, 0, s, spec, NS, TX, sp, t);
-    else hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_PRECOND>), grid, block, 0, s, spec, NS, TX, sp, t);
+    constexpr int R = zspec_radix<T, L>();
+    if (op == ZOP_GRAD)
+        hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_GRAD, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX, sp, t);
+    else if (op == ZOP_DIV)
+        hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_DIV, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX, sp, t);
+    else
+        hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_PRECOND, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX,
+                           sp, t);
 }
 
-template <typename T> int launch_zspec(int op, const SpecParams& sp, long NS, void* spec, const void* tw, hipStream_t s)
+template <typename T>
+int launch_zspec(int op, const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s)
 {
     const int M = sp.n1 / 2;
     const cx_t<T>* t = (const cx_t<T>*)tw;
     cx_t<T>* d = (cx_t<T>*)spec;
+    constexpr int BLK = zspec_block<T>();
     if (sp.n3 == 1) {
-        const int TX = M < kBlock ? M : kBlock;
-        zspec_dispatch<T, 1>(op, dim3(M / TX, sp.n2), dim3(TX), s, d, NS, TX, sp, t);
+        const int TX = M < BLK ? M : BLK;
+        zspec_dispatch<T, 1, BLK, 0>(op, dim3(M / TX, sp.n2), dim3(TX), s, d, lay, TX, sp, t);
     } else {
-        const int TX = col_tile(sp.n3, M);
         NM_SIZE_SWITCH(sp.n3, {
-            constexpr int R = NN >= 8 ? 8 : NN;
-            zspec_dispatch<T, NN>(op, dim3(M / TX, sp.n2), dim3(TX * (NN / R)), s, d, NS, TX, sp, t);
+            constexpr int G = NN / zspec_radix<T, NN>();
+            constexpr int TXP = BLK / G;
+            if (M >= TXP)
+                zspec_dispatch<T, NN, BLK, TXP>(op, dim3(M / TXP, sp.n2), dim3(TXP * G), s, d, lay, TXP, sp, t);
+            else
+                zspec_dispatch<T, NN, BLK, 0>(op, dim3(1, sp.n2), dim3(M * G), s, d, lay, M, sp, t);
+        })
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+#ifndef NM_COLOP_R64
+#define NM_COLOP_R64 16
+#endif
+template <typename T, int L> constexpr int colop_radix()
+{
+    return L < 16 ? L : (sizeof(T) == 8 ? (NM_COLOP_R64 < L ? NM_COLOP_R64 : L) : 16);
+}
+
+template <typename T, int L, int TXC>
+static void colop_dispatch(int op, dim3 grid, dim3 block, hipStream_t s, cx_t<T>* S, cx_t<T>* S2, long rowstride,
+                           long cs, int TX, const SpecParams& sp, const cx_t<T>* t)
+{
+    constexpr int R = colop_radix<T, L>();
+    switch (op) {
+    case YOP_DERIV:
+        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DERIV, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
+                           t);
+        break;
+    case YOP_DIV:
+        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DIV, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp, t);
+        break;
+    case ZOP_STRAIN:
+        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_STRAIN, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
+                           t);
+        break;
+    default:
+        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_DIVZ, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
+                           t);
+        break;
+    }
+}
+
+template <typename T>
+int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, void* S2, const void* tw,
+                 hipStream_t s)
+{
+    const int M = lay.M;
+    const cx_t<T>* t = (const cx_t<T>*)tw;
+    cx_t<T>* a = (cx_t<T>*)S;
+    cx_t<T>* b = (cx_t<T>*)S2;
+    const bool yax = (op == YOP_DERIV || op == YOP_DIV);
+    const int L = yax ? lay.n2 : lay.n3;
+    const int planes = yax ? lay.n3 : lay.n2;
+    if (L == 1) {
+        const int TX = M < 256 ? M : 256;
+        colop_dispatch<T, 1, 0>(op, dim3(M / TX, planes), dim3(TX), s, a, b, lay.ps, lay.cs, TX, sp, t);
+    } else {
+        NM_SIZE_SWITCH(L, {
+            constexpr int G = NN / colop_radix<T, NN>();
+            constexpr int TXP = 256 / G;
+            if (M >= TXP)
+                colop_dispatch<T, NN, TXP>(op, dim3(M / TXP, planes), dim3(TXP * G), s, a, b, lay.ps, lay.cs, TXP, sp,
+                                           t);
+            else
+                colop_dispatch<T, NN, 0>(op, dim3(1, planes), dim3(M * G), s, a, b, lay.ps, lay.cs, M, sp, t);
         })
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -636,9 +898,11 @@ template <typename T> int launch_zspec(int op, const SpecParams& sp, long NS, vo
 #define NM_INST(T)                                                                                                     \
     template int launch_xfwd<T>(int, int, const XFwdArgs&, const void*, hipStream_t);                                  \
     template int launch_xinv<T>(int, int, const XInvArgs&, const void*, hipStream_t);                                  \
-    template int launch_xstress<T>(int, void*, long, long, const uint16_t*, const void*, const void*, hipStream_t);    \
-    template int launch_ypass<T>(int, int, int, int, int, long, void*, const void*, hipStream_t);                      \
-    template int launch_zspec<T>(int, const SpecParams&, long, void*, const void*, hipStream_t);
+    template int launch_xstress<T>(int, void*, const SpecLayout&, const uint16_t*, const void*, const void*,          \
+                                   hipStream_t);                                                                       \
+    template int launch_ypass<T>(int, int, const SpecLayout&, void*, const void*, hipStream_t);                        \
+    template int launch_zspec<T>(int, const SpecParams&, const SpecLayout&, void*, const void*, hipStream_t);        \
+    template int launch_colop<T>(int, const SpecParams&, const SpecLayout&, void*, void*, const void*, hipStream_t);
 NM_INST(double)
 NM_INST(float)
 

@@ -264,7 +264,7 @@ def green_matrix(ctx: Context) -> np.ndarray:
     return G
 
 
-OPERATOR_PASSES = ("x_fwd", "y_fwd3", "z_grad", "y_inv6", "x_stress", "y_fwd6", "z_div", "y_inv3", "x_inv_inertia")
+OPERATOR_PASSES = ("x_fwd", "y_deriv", "z_strain", "x_stress", "y_div", "z_div", "x_inv_inertia")
 PRECOND_PASSES = ("x_fwd", "y_fwd3", "z_precond", "y_inv3", "x_inv")
 
 
