@@ -171,14 +171,13 @@ def main():
         f"dt {pb.dt:.4f}, fc {pb.pulse_fc:.4f}, |Gamma| {pb.gamma_idx.size}")
 
     variants = {}
+    starts = {"prev": nmb.WS_PREV, "cold": nmb.WS_COLD, "taylor": nmb.WS_TAYLOR}
     for v in args.variants.split(","):
-        if v == "fp64":
-            o = nmb.Options(tol=1e-8, max_iter=500, warm_start=nmb.WS_PREV)
-        elif v == "mixed":
-            o = nmb.Options(tol=1e-8, max_iter=500, warm_start=nmb.WS_PREV, precision=nmb.PREC_MIXED,
-                            inner_tol=1e-4)
-        else:
+        prec, _, start = v.partition("_")
+        if prec not in ("fp64", "mixed") or (start and start not in starts):
             raise SystemExit(f"unknown variant {v}")
+        o = nmb.Options(tol=1e-8, max_iter=500, warm_start=starts[start or "prev"],
+                        precision=nmb.PREC_MIXED if prec == "mixed" else nmb.PREC_FP64, inner_tol=1e-4)
         variants[v] = run_variant(pb, o, args.steps, args.warmup, v)
 
     op = {} if args.skip_operator else operator_rates(pb)

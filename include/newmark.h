@@ -147,6 +147,61 @@ int nm_green_matrix(const nm_ctx* ctx, double* G);
  * for nm_apply_operator.  Synchronous. */
 int nm_profile_passes(nm_ctx* ctx, int which, const void* u_dev, void* out_dev, int dtype, int reps, double* ms);
 
+/* ------------------------------------------------------------------------
+ * Learned warm start (an addition to the paper's method): a periodic 3D
+ * convolutional network, 4 layers of 3x3x3 kernels, 16 hidden channels,
+ * leaky ReLU (slope 0.1), BF16 weights and activations with FP32
+ * accumulation on the matrix cores.  It predicts the correction to the
+ * Newmark predictor u~ = u_n + dt v_n + dt^2 (1/2 - beta) a_n:
+ *     x0 = u~ + s * net(f),   s = rms(u~ - u_n),
+ * with per-voxel features f (BF16, 32 channels, channels-last [N][32]):
+ * u_n/s, dt v_n/s, dt^2 (1/2 - beta) a_n/s (the Newmark state),
+ * rho/rhobar, C_voigt/Cbar_11 (21), 0.
+ * The Krylov solve still runs to the same tolerance; only the initial
+ * iterate changes.  Grids for the network: every axis a power of two and
+ * n1 >= 16.  A network object is independent of any solver context.
+ * ------------------------------------------------------------------------ */
+typedef struct nm_net nm_net;
+
+/* Create a network with seeded random weights (FP32 master copy on the device). */
+int nm_net_create(unsigned long long seed, nm_net** out);
+void nm_net_destroy(nm_net* net);
+/* Number of FP32 parameters: per layer W[cout][cin][3][3][3] (taps z, y, x) then b[cout];
+ * layers 31->16->16->16->3. */
+long nm_net_num_params(const nm_net* net);
+int nm_net_get_params(const nm_net* net, float* w);
+/* Replace the parameters (host FP32); resets the optimizer state. */
+int nm_net_set_params(nm_net* net, const float* w);
+/* pred (device FP32 [N][4], components 0..2) = net(feat) for features feat (device BF16 [N][32]). */
+int nm_net_forward(nm_net* net, void* hip_stream, const int* grid, const void* feat_dev, void* pred_dev);
+/* One Adam step (lr, beta1 0.9, beta2 0.999) on the mean squared error between
+ * net(feat) and target (device FP32 [N][4]); loss (may be NULL) receives the
+ * loss before the update.  Synchronous. */
+int nm_net_train_step(nm_net* net, void* hip_stream, const int* grid, const void* feat_dev, const void* target_dev,
+                      float lr, float* loss);
+/* Gradients of that loss with respect to every parameter (host FP32, nm_net_num_params entries). */
+int nm_net_gradients(nm_net* net, void* hip_stream, const int* grid, const void* feat_dev, const void* target_dev,
+                     float* grad_host, float* loss);
+/* One periodic 3x3x3 convolution layer on caller buffers (checks of the matrix-core kernels).
+ * Weights w: host FP32 [cout][cin][27]; bias host FP32 [cout] or NULL.
+ *   mode 0: out (device FP32 [N][16]) = conv(x), x device BF16 [N][cinp]
+ *   mode 1: out (device FP32 [N][16]) = transposed conv of dy (device BF16 [N][16]); cinp == 16
+ *   mode 2: dw_host [cout][cin][27], db_host [cout] = weight and bias gradients for input x and dy
+ * cinp is 16 or 32, cin <= cinp, cout <= 16.  Synchronous. */
+int nm_conv3d_bf16(void* hip_stream, int mode, const int* grid, int cinp, int cin, int cout, const void* x_dev,
+                   const void* w_fp32_host, const float* bias_host, const void* dy_dev, void* out_dev, float* dw_host,
+                   float* db_host);
+
+/* Attach a network to a solver context (not owned; NULL detaches).  Needed by
+ * NM_WS_LEARNED and by the two training-sample calls below. */
+int nm_ws_attach(nm_ctx* ctx, nm_net* net);
+/* Between steps: features (device BF16 [N][32]) of the next step from the current
+ * Newmark state (u_n, v_n, a_n); stores the scale s in the context. */
+int nm_ws_features(nm_ctx* ctx, void* feat_dev);
+/* After the following nm_newmark_step: the training target (u_{n+1} - u~) / s as
+ * device FP32 [N][4]. */
+int nm_ws_target(nm_ctx* ctx, void* target_dev);
+
 /* The HIP stream (hipStream_t) all of the context's work is queued on. */
 void* nm_get_stream(nm_ctx* ctx);
 

@@ -8,7 +8,7 @@
 #include "nm_fft.h"
 #include "nm_passes.h"
 #include "nm_vec.h"
-#include "nm_warm.h"
+#include "nm_net.h"
 
 #include <algorithm>
 #include <chrono>
@@ -74,7 +74,12 @@ struct nm_ctx {
     int64_t step = 0;
     std::string err;
     std::vector<void*> allocs;
-    nm::WarmNet* warm = nullptr;
+    // learned warm start (network attached by nm_ws_attach, not owned)
+    nm_net* net = nullptr;
+    uint16_t* feat = nullptr;
+    float* matf = nullptr;
+    double* wscale = nullptr;
+    double* wred = nullptr;
 };
 
 namespace {
@@ -519,6 +524,27 @@ template <typename T> int profile_impl(nm_ctx* c, int which, const T* in, T* out
     return NM_OK;
 }
 
+nm::WarmArgs warm_args(nm_ctx* c)
+{
+    nm::WarmArgs a{};
+    a.n1 = c->n1;
+    a.n2 = c->n2;
+    a.n3 = c->n3;
+    a.N = c->N;
+    a.u = c->u;
+    a.v = c->v;
+    a.a = c->a;
+    a.ut = c->ut;
+    a.dt = c->dt;
+    a.c2 = c->dt * c->dt * (0.5 - c->beta);
+    a.phase = c->phase;
+    a.matf = c->matf;
+    a.red = c->wred;
+    a.scale = c->wscale;
+    a.feat = c->feat;
+    return a;
+}
+
 } // namespace
 
 extern "C" {
@@ -529,7 +555,6 @@ void nm_destroy(nm_ctx* c)
 {
     if (!c) return;
     if (c->stream) (void)hipStreamSynchronize(c->stream);
-    if (c->warm) nm::warm_destroy(c->warm);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
@@ -745,10 +770,10 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     case NM_WS_COLD: LCHK(c, launch_fill<double>(c->w, 0.0, n, s)); break;
     case NM_WS_TAYLOR: LCHK(c, launch_taylor(c->w, c->u, c->v, c->a, n, c->dt, s)); break;
     case NM_WS_LEARNED: {
-        if (!c->warm) return fail(c, NM_EINVAL, "learned warm start requested but no network weights are set");
+        if (!c->net) return fail(c, NM_EINVAL, "learned warm start requested but no network is attached");
         auto tw0 = std::chrono::steady_clock::now();
-        int e = nm::warm_predict(c->warm, c->u, c->v, c->a, c->w, c->dt, s);
-        if (e) return fail(c, NM_EHIP, "warm-start network failed");
+        int e = nm::warm_predict(c->net, warm_args(c), c->w, s);
+        if (e) return fail(c, e == -1 ? NM_EUNSUPPORTED : NM_EHIP, "warm-start network failed");
         HIPCHK(c, hipStreamSynchronize(s));
         t_warm = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw0).count();
         break;
@@ -929,6 +954,49 @@ int nm_profile_passes(nm_ctx* c, int which, const void* u_dev, void* out_dev, in
     if (dtype == NM_FP64) return profile_impl<double>(c, which, (const double*)u_dev, (double*)out_dev, reps, ms);
     if (dtype == NM_FP32) return profile_impl<float>(c, which, (const float*)u_dev, (float*)out_dev, reps, ms);
     return fail(c, NM_EINVAL, "dtype must be NM_FP64 or NM_FP32");
+}
+
+int nm_ws_attach(nm_ctx* c, nm_net* net)
+{
+    if (!c) return NM_EINVAL;
+    c->net = net;
+    if (!net || c->feat) return NM_OK;
+    CHK(dalloc(c, &c->feat, 32 * (size_t)c->N));
+    CHK(dalloc(c, &c->matf, 22 * (size_t)c->nph));
+    CHK(dalloc(c, &c->wscale, 1));
+    CHK(dalloc(c, &c->wred, 512));
+    std::vector<double> C(21 * (size_t)c->nph), rho(c->nph);
+    HIPCHK(c, hipMemcpy(C.data(), c->C64, C.size() * sizeof(double), hipMemcpyDeviceToHost));
+    HIPCHK(c, hipMemcpy(rho.data(), c->rho64, rho.size() * sizeof(double), hipMemcpyDeviceToHost));
+    std::vector<float> mf(22 * (size_t)c->nph);
+    const double c11 = c->sp.Cbar[0] > 0 ? c->sp.Cbar[0] : 1.0;
+    for (int g = 0; g < c->nph; g++) {
+        mf[22 * g] = (float)(rho[g] / c->sp.rhobar);
+        for (int k = 0; k < 21; k++) mf[22 * g + 1 + k] = (float)(C[21 * g + k] / c11);
+    }
+    HIPCHK(c, hipMemcpy(c->matf, mf.data(), mf.size() * sizeof(float), hipMemcpyHostToDevice));
+    return NM_OK;
+}
+
+int nm_ws_features(nm_ctx* c, void* feat_dev)
+{
+    if (!c || !c->feat) return fail(c, NM_EINVAL, "call nm_ws_attach first");
+    hipStream_t s = c->stream;
+    // predictor of the next step (the step recomputes the same values)
+    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    nm::WarmArgs a = warm_args(c);
+    if (feat_dev) a.feat = (uint16_t*)feat_dev;
+    LCHK(c, nm::warm_features(a, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return NM_OK;
+}
+
+int nm_ws_target(nm_ctx* c, void* target_dev)
+{
+    if (!c || !c->feat || !target_dev) return fail(c, NM_EINVAL, "call nm_ws_attach first");
+    LCHK(c, nm::warm_target(warm_args(c), c->u, (float*)target_dev, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NM_OK;
 }
 
 void* nm_get_stream(nm_ctx* c) { return c ? (void*)c->stream : nullptr; }

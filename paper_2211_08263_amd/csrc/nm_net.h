@@ -1,0 +1,35 @@
+// Solver-side interface of the learned warm start (implemented in nm_net.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define CHECK_NM(expr)                                                                                                 \
+    do {                                                                                                               \
+        int e_ = (expr);                                                                                               \
+        if (e_ != 0) return e_;                                                                                        \
+    } while (0)
+
+struct nm_net;
+
+namespace nm {
+
+struct WarmArgs {
+    int n1, n2, n3;
+    long N;
+    const double* u;       // u_n, SoA 3 x N
+    const double* v;       // v_n
+    const double* a;       // a_n
+    const double* ut;      // Newmark predictor of the next step
+    double dt, c2;         // dt and dt^2 (1/2 - beta)
+    const uint16_t* phase; // grain id per voxel
+    const float* matf;     // per phase: rho / rhobar, C_voigt[21] / Cbar_11
+    double* red;           // >= 512 partial sums
+    double* scale;         // one double: rms(u~ - u_n)
+    uint16_t* feat;        // BF16 [N][32]
+};
+
+int warm_features(const WarmArgs& a, hipStream_t s);
+int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s);
+int warm_target(const WarmArgs& a, const double* unext, float* target, hipStream_t s);
+
+} // namespace nm

@@ -1,0 +1,762 @@
+// Learned warm start: a small periodic 3D convolutional network (3x3x3
+// kernels, 16 hidden channels, leaky ReLU) that predicts the correction to
+// the Newmark predictor u~ = u + dt v + dt^2 (1/2 - beta) a:
+//     x0 = u~ + s * net(features),  s = rms(u~ - u_n)
+// features (channels-last BF16, 32 per voxel): u_n/s, dt v_n/s,
+// dt^2 (1/2 - beta) a_n/s (the Newmark state, 9), rho/rhobar (1),
+// C/Cbar_11 (21), 0 (1).
+//
+// Convolutions are implicit GEMMs on the BF16 matrix cores (MFMA 16x16x16,
+// FP32 accumulation): a wave computes 16 consecutive voxels along x x 16
+// output channels, looping over the 27 taps and the input-channel chunks.
+// Operand layouts (per lane l, r = l % 16, g = l / 16):
+//   A[row = r][k = 4g + i],  B[k = 4g + i][col = r],  D[row = 4g + i][col = r].
+#include "../../include/newmark.h"
+#include "nm_common.h"
+#include "nm_net.h"
+
+#include <cmath>
+#include <cstring>
+#include <random>
+#include <vector>
+
+namespace nm {
+
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float kLeak = 0.1f;
+constexpr int kFeat = 32;   // padded feature channels
+constexpr int kHid = 16;    // hidden channels (also the padded MFMA N)
+constexpr int kOutC = 3;    // predicted displacement components
+constexpr int kPredStride = 4;
+
+__host__ __device__ inline uint16_t f2bf(float f)
+{
+    uint32_t u;
+    memcpy(&u, &f, 4);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)(u >> 16); // inf / nan
+    u += 0x7fffu + ((u >> 16) & 1u);                                   // round to nearest even
+    return (uint16_t)(u >> 16);
+}
+__host__ __device__ inline float bf2f(uint16_t h)
+{
+    uint32_t u = (uint32_t)h << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+struct Grid {
+    int n1, n2, n3;
+    long N;
+};
+
+__device__ __forceinline__ long tap_voxel(int x, int y, int z, int t, const Grid& g)
+{
+    const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+    const int xx = (x + dx) & (g.n1 - 1), yy = (y + dy) & (g.n2 - 1), zz = (z + dz) & (g.n3 - 1);
+    return ((long)zz * g.n2 + yy) * g.n1 + xx;
+}
+
+// ---------------------------------------------------------------------------
+// Forward convolution: Y[v][co] = b[co] + sum_{tap, ci} W[tap][co][ci] X[v + d(tap)][ci]
+//   X: BF16 [N][CINP], W: BF16 [27][16][CINP] (co padded to 16), bias FP32 [16].
+// Epilogues: EPI_BF16_ACT  -> BF16 [N][16], leaky ReLU
+//            EPI_F32       -> FP32 [N][ostride] (channels < cout), no activation
+//            EPI_BF16_DACT -> BF16 [N][16] times leaky'(Aprev) (backward data pass)
+// ---------------------------------------------------------------------------
+enum { EPI_BF16_ACT = 0, EPI_F32 = 1, EPI_BF16_DACT = 2 };
+
+template <int CINP, int EPI>
+__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X, const uint16_t* __restrict__ W,
+                                                  const float* __restrict__ bias, void* __restrict__ Y,
+                                                  const uint16_t* __restrict__ Aprev, Grid g, int cout, int ostride,
+                                                  long tiles_per_wave)
+{
+    constexpr int KC = CINP / 16;
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int r = lane & 15, gq = lane >> 4;
+    bf16x4 wb[27][KC];
+#pragma unroll
+    for (int t = 0; t < 27; t++)
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++) wb[t][kc] = *(const bf16x4*)(W + ((long)(t * 16 + r) * CINP + kc * 16 + 4 * gq));
+    const float bcol = (bias && r < cout) ? bias[r] : 0.0f;
+    const long ntiles = g.N / 16;
+    const long t0 = wave * tiles_per_wave;
+    const long t1 = t0 + tiles_per_wave < ntiles ? t0 + tiles_per_wave : ntiles;
+    for (long tile = t0; tile < t1; tile++) {
+        const long v0 = tile * 16;
+        const int x0 = (int)(v0 & (g.n1 - 1));
+        const long yz = v0 / g.n1;
+        const int y = (int)(yz % g.n2), z = (int)(yz / g.n2);
+        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
+            const long vox = tap_voxel(x0 + r, y, z, t, g);
+#pragma unroll
+            for (int kc = 0; kc < KC; kc++) {
+                const bf16x4 a = *(const bf16x4*)(X + vox * CINP + kc * 16 + 4 * gq);
+                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wb[t][kc], acc, 0, 0, 0);
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const long v = v0 + 4 * gq + i;
+            float o = acc[i] + bcol;
+            if constexpr (EPI == EPI_BF16_ACT) {
+                o = o > 0.f ? o : kLeak * o;
+                ((uint16_t*)Y)[v * kHid + r] = f2bf(o);
+            } else if constexpr (EPI == EPI_BF16_DACT) {
+                const float ap = bf2f(Aprev[v * kHid + r]);
+                o = ap > 0.f ? o : kLeak * o;
+                ((uint16_t*)Y)[v * kHid + r] = f2bf(o);
+            } else {
+                if (r < cout) ((float*)Y)[v * ostride + r] = o;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Weight gradient: dW[co][ci][tap] = sum_v dZ[v][co] X[v + d(tap)][ci]  (MFMA with
+// K = voxels), bias gradient db[co] = sum_v dZ[v][co].  Each wave writes its
+// partial sums; k_reduce_partials adds them in a fixed order.
+//   partial layout per wave: [27][KC][64 lanes][4] then [64 lanes] (bias)
+// ---------------------------------------------------------------------------
+template <int CINP>
+__global__ __launch_bounds__(256) void k_conv_bwdw(const uint16_t* __restrict__ X, const uint16_t* __restrict__ DZ,
+                                                   float* __restrict__ partial, Grid g, long tiles_per_wave)
+{
+    constexpr int KC = CINP / 16;
+    constexpr long PW = 27L * KC * 256 + 64;
+    const int lane = threadIdx.x & 63;
+    const long wave = (long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    const int r = lane & 15, gq = lane >> 4;
+    const long ntiles = g.N / 16;
+    // waves past the last tile range own no partial slot
+    if (wave * tiles_per_wave >= ntiles) return;
+    f32x4 acc[27][KC];
+#pragma unroll
+    for (int t = 0; t < 27; t++)
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++) acc[t][kc] = f32x4{0.f, 0.f, 0.f, 0.f};
+    float bsum = 0.f;
+    const long t0 = wave * tiles_per_wave;
+    const long t1 = t0 + tiles_per_wave < ntiles ? t0 + tiles_per_wave : ntiles;
+    for (long tile = t0; tile < t1; tile++) {
+        const long v0 = tile * 16;
+        const int x0 = (int)(v0 & (g.n1 - 1));
+        const long yz = v0 / g.n1;
+        const int y = (int)(yz % g.n2), z = (int)(yz / g.n2);
+        bf16x4 b;
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            const uint16_t h = DZ[(v0 + 4 * gq + i) * kHid + r];
+            b[i] = (short)h;
+            bsum += bf2f(h);
+        }
+#pragma unroll
+        for (int t = 0; t < 27; t++) {
+            long vs[4];
+#pragma unroll
+            for (int i = 0; i < 4; i++) vs[i] = tap_voxel(x0 + 4 * gq + i, y, z, t, g);
+#pragma unroll
+            for (int kc = 0; kc < KC; kc++) {
+                bf16x4 a;
+#pragma unroll
+                for (int i = 0; i < 4; i++) a[i] = (short)X[vs[i] * CINP + kc * 16 + r];
+                acc[t][kc] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t][kc], 0, 0, 0);
+            }
+        }
+    }
+    float* out = partial + wave * PW;
+#pragma unroll
+    for (int t = 0; t < 27; t++)
+#pragma unroll
+        for (int kc = 0; kc < KC; kc++)
+#pragma unroll
+            for (int i = 0; i < 4; i++) out[((long)(t * KC + kc) * 64 + lane) * 4 + i] = acc[t][kc][i];
+    out[27L * KC * 256 + lane] = bsum;
+}
+
+// Sum the per-wave partials (fixed order) and scatter into dW[co][ci][tap], db[co].
+// D element (lane l, reg i) of chunk kc = [row ci = kc*16 + 4*(l/16) + i][col co = l % 16].
+template <int CINP>
+__global__ void k_reduce_bwdw(const float* __restrict__ partial, int nwaves, float* __restrict__ dW,
+                              float* __restrict__ db, int cin, int cout)
+{
+    constexpr int KC = CINP / 16;
+    constexpr long PW = 27L * KC * 256 + 64;
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < 27L * KC * 256) {
+        float s = 0.f;
+        for (int w = 0; w < nwaves; w++) s += partial[w * PW + e];
+        const int i = (int)(e % 4), lane = (int)((e / 4) % 64), tk = (int)(e / 256);
+        const int t = tk / KC, kc = tk % KC;
+        const int ci = kc * 16 + 4 * (lane / 16) + i, co = lane % 16;
+        if (ci < cin && co < cout) dW[((long)co * cin + ci) * 27 + t] = s;
+    } else if (e < 27L * KC * 256 + 16) {
+        const int co = (int)(e - 27L * KC * 256);
+        float s = 0.f;
+        for (int w = 0; w < nwaves; w++)
+            for (int q = 0; q < 4; q++) s += partial[w * PW + 27L * KC * 256 + co + 16 * q];
+        if (co < cout) db[co] = s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Loss: L = mean over voxels and components of (pred - target)^2;
+// dZ = dL/dpred as BF16 [N][16] (channels >= 3 zero).  Per-block partial sums.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_loss(const float* __restrict__ pred, const float* __restrict__ target,
+                                              uint16_t* __restrict__ dz, long N, double* partials)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    const float sc = 2.0f / (float)(3.0 * (double)N);
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
+        uint16_t o[kHid];
+#pragma unroll
+        for (int c = 0; c < kHid; c++) o[c] = 0;
+#pragma unroll
+        for (int c = 0; c < kOutC; c++) {
+            const float d = pred[v * kPredStride + c] - target[v * kPredStride + c];
+            acc += (double)d * d;
+            o[c] = f2bf(sc * d);
+        }
+#pragma unroll
+        for (int c = 0; c < kHid; c++) dz[v * kHid + c] = o[c];
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = (sh[0] + sh[1] + sh[2] + sh[3]) / (3.0 * (double)N);
+}
+
+// ---------------------------------------------------------------------------
+// Adam on the FP32 master parameters, then BF16 packing of the weights.
+// ---------------------------------------------------------------------------
+__global__ void k_adam(float* __restrict__ p, const float* __restrict__ gr, float* __restrict__ m,
+                       float* __restrict__ v, long n, float lr, float b1, float b2, float eps, float c1, float c2)
+{
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float gi = gr[i];
+    const float mi = b1 * m[i] + (1.f - b1) * gi;
+    const float vi = b2 * v[i] + (1.f - b2) * gi * gi;
+    m[i] = mi;
+    v[i] = vi;
+    p[i] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+
+// Forward layout Wf[tap][16][cinp] (co padded) and backward-data layout
+// Wb[tap'][16 (ci)][16 (co)] = W[co][ci][26 - tap'] (flipped taps, transposed).
+__global__ void k_pack(const float* __restrict__ W, int cin, int cout, int cinp, uint16_t* __restrict__ Wf,
+                       uint16_t* __restrict__ Wb)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    const int nf = 27 * 16 * cinp;
+    if (e < nf) {
+        const int ci = e % cinp, co = (e / cinp) % 16, t = e / (16 * cinp);
+        Wf[e] = (ci < cin && co < cout) ? f2bf(W[((long)co * cin + ci) * 27 + t]) : (uint16_t)0;
+    }
+    if (Wb && e < 27 * 256) {
+        const int co = e % 16, ci = (e / 16) % 16, t = e / 256;
+        Wb[e] = (ci < cin && co < cout) ? f2bf(W[((long)co * cin + ci) * 27 + (26 - t)]) : (uint16_t)0;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Features and prediction
+// ---------------------------------------------------------------------------
+// partial sums of |u~ - u|^2 (u~ = predictor), for the scale s
+__global__ __launch_bounds__(256) void k_incr_norm(const double* __restrict__ ut, const double* __restrict__ u, long n,
+                                                   double* partials)
+{
+    __shared__ double sh[4];
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double d = ut[i] - u[i];
+        acc += d * d;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) partials[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
+}
+
+__global__ void k_sum_scale(const double* __restrict__ partials, int n, long count, double* scale)
+{
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        double s = 0.0;
+        for (int i = 0; i < n; i++) s += partials[i];
+        // s = 0 before anything moves: features are zero and the correction vanishes
+        scale[0] = sqrt(s / (double)count);
+    }
+}
+
+__global__ __launch_bounds__(256) void k_features(const double* __restrict__ u, const double* __restrict__ v,
+                                                  const double* __restrict__ a, double dt, double c2,
+                                                  const uint16_t* __restrict__ phase, const float* __restrict__ matf,
+                                                  long N, const double* __restrict__ scale, uint16_t* __restrict__ X)
+{
+    const double inv = scale[0] > 0.0 ? 1.0 / scale[0] : 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+        uint16_t f[kFeat];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            f[c] = f2bf((float)(u[c * N + i] * inv));
+            f[3 + c] = f2bf((float)(dt * v[c * N + i] * inv));
+            f[6 + c] = f2bf((float)(c2 * a[c * N + i] * inv));
+        }
+        const float* mf = matf + 22 * (long)phase[i];
+#pragma unroll
+        for (int c = 0; c < 22; c++) f[9 + c] = f2bf(mf[c]);
+        f[31] = 0;
+#pragma unroll
+        for (int c = 0; c < kFeat; c += 4) {
+            uint64_t w = (uint64_t)f[c] | ((uint64_t)f[c + 1] << 16) | ((uint64_t)f[c + 2] << 32) |
+                         ((uint64_t)f[c + 3] << 48);
+            *(uint64_t*)(X + i * kFeat + c) = w;
+        }
+    }
+}
+
+// x0 = u~ + s * pred (SoA FP64 out)
+__global__ __launch_bounds__(256) void k_predict(const double* __restrict__ ut, const float* __restrict__ pred,
+                                                 const double* __restrict__ scale, double* __restrict__ x0, long N)
+{
+    const double s = scale[0];
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x)
+#pragma unroll
+        for (int c = 0; c < 3; c++) x0[c * N + v] = ut[c * N + v] + s * (double)pred[v * kPredStride + c];
+}
+
+// target = (u_next - u~) / s  as FP32 [N][4]
+__global__ __launch_bounds__(256) void k_target(const double* __restrict__ unext, const double* __restrict__ ut,
+                                                const double* __restrict__ scale, float* __restrict__ target, long N)
+{
+    const double inv = scale[0] > 0.0 ? 1.0 / scale[0] : 0.0;
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
+#pragma unroll
+        for (int c = 0; c < 3; c++) target[v * kPredStride + c] = (float)((unext[c * N + v] - ut[c * N + v]) * inv);
+        target[v * kPredStride + 3] = 0.f;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+static int launch_conv(int cinp, int epi, const uint16_t* X, const uint16_t* W, const float* bias, void* Y,
+                       const uint16_t* Aprev, const Grid& g, int cout, int ostride, hipStream_t s)
+{
+    const long ntiles = g.N / 16;
+    long waves = 2048;
+    if (waves > ntiles) waves = ntiles;
+    const long tpw = (ntiles + waves - 1) / waves;
+    waves = (ntiles + tpw - 1) / tpw;
+    const int blocks = (int)((waves + 3) / 4);
+    if (cinp == 32 && epi == EPI_BF16_ACT)
+        hipLaunchKernelGGL((k_conv_fwd<32, EPI_BF16_ACT>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g,
+                           cout, ostride, tpw);
+    else if (cinp == 32 && epi == EPI_F32)
+        hipLaunchKernelGGL((k_conv_fwd<32, EPI_F32>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
+                           ostride, tpw);
+    else if (cinp == 16 && epi == EPI_BF16_ACT)
+        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_ACT>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g,
+                           cout, ostride, tpw);
+    else if (cinp == 16 && epi == EPI_F32)
+        hipLaunchKernelGGL((k_conv_fwd<16, EPI_F32>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
+                           ostride, tpw);
+    else if (cinp == 16 && epi == EPI_BF16_DACT)
+        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_DACT>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g,
+                           cout, ostride, tpw);
+    else return -1;
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+static long bwdw_waves(long ntiles) { return ntiles < 1024 ? ntiles : 1024; }
+
+static int launch_bwdw(int cinp, const uint16_t* X, const uint16_t* DZ, float* partial, float* dW, float* db, int cin,
+                       int cout, const Grid& g, hipStream_t s)
+{
+    const long ntiles = g.N / 16;
+    long waves = bwdw_waves(ntiles);
+    const long tpw = (ntiles + waves - 1) / waves;
+    waves = (ntiles + tpw - 1) / tpw;
+    const int blocks = (int)((waves + 3) / 4);
+    const long nout = 27L * (cinp / 16) * 256 + 16;
+    if (cinp == 32) {
+        hipLaunchKernelGGL((k_conv_bwdw<32>), dim3(blocks), dim3(256), 0, s, X, DZ, partial, g, tpw);
+        hipLaunchKernelGGL((k_reduce_bwdw<32>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, partial,
+                           (int)waves, dW, db, cin, cout);
+    } else {
+        hipLaunchKernelGGL((k_conv_bwdw<16>), dim3(blocks), dim3(256), 0, s, X, DZ, partial, g, tpw);
+        hipLaunchKernelGGL((k_reduce_bwdw<16>), dim3((unsigned)((nout + 255) / 256)), dim3(256), 0, s, partial,
+                           (int)waves, dW, db, cin, cout);
+    }
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+} // namespace nm
+
+using namespace nm;
+
+// Network: layer l has cin_l -> cout_l, cinp_l padded input channels.
+struct nm_net {
+    int L = 4;
+    int cin[4] = {31, 16, 16, 16}, cout[4] = {16, 16, 16, 3}, cinp[4] = {32, 16, 16, 16};
+    long off[5] = {0, 0, 0, 0, 0}; // parameter offsets: W then b per layer
+    long nparam = 0;
+    float *p = nullptr, *gr = nullptr, *m = nullptr, *v = nullptr; // device FP32
+    uint16_t* wf[4] = {};                                         // forward BF16
+    uint16_t* wb[4] = {};                                         // backward-data BF16
+    long step = 0;
+    // workspace (grown on demand)
+    long capN = 0;
+    uint16_t* act[4] = {}; // act[0] unused (features are the input), act[1..3] hidden
+    uint16_t *dz0 = nullptr, *dz1 = nullptr;
+    float* pred = nullptr;
+    float* partial = nullptr;
+    long cap_partial = 0;
+    double* red = nullptr;
+    double* hred = nullptr;
+    std::vector<void*> ws_allocs;
+};
+
+static long layer_w(const nm_net* n, int l) { return (long)n->cout[l] * n->cin[l] * 27; }
+
+static int net_alloc(void** p, size_t bytes, std::vector<void*>* list)
+{
+    if (hipMalloc(p, bytes) != hipSuccess) return NM_ENOMEM;
+    if (list) list->push_back(*p);
+    return NM_OK;
+}
+
+static int net_pack(nm_net* n, hipStream_t s)
+{
+    for (int l = 0; l < n->L; l++) {
+        const int nf = 27 * 16 * n->cinp[l];
+        const int tot = nf > 27 * 256 ? nf : 27 * 256;
+        hipLaunchKernelGGL(k_pack, dim3((tot + 255) / 256), dim3(256), 0, s, n->p + n->off[l], n->cin[l],
+                           n->cout[l], n->cinp[l], n->wf[l], l > 0 ? n->wb[l] : nullptr);
+    }
+    return hipGetLastError() == hipSuccess ? NM_OK : NM_EHIP;
+}
+
+static int net_workspace(nm_net* n, long N)
+{
+    if (N <= n->capN) return NM_OK;
+    for (void* q : n->ws_allocs) (void)hipFree(q);
+    n->ws_allocs.clear();
+    n->capN = 0;
+    for (int l = 1; l < 4; l++) CHECK_NM(net_alloc((void**)&n->act[l], N * kHid * 2, &n->ws_allocs));
+    CHECK_NM(net_alloc((void**)&n->dz0, N * kHid * 2, &n->ws_allocs));
+    CHECK_NM(net_alloc((void**)&n->dz1, N * kHid * 2, &n->ws_allocs));
+    CHECK_NM(net_alloc((void**)&n->pred, N * kPredStride * 4, &n->ws_allocs));
+    const long waves = bwdw_waves(N / 16);
+    CHECK_NM(net_alloc((void**)&n->partial, waves * (27L * 2 * 256 + 64) * 4, &n->ws_allocs));
+    CHECK_NM(net_alloc((void**)&n->red, 4096 * sizeof(double), &n->ws_allocs));
+    n->capN = N;
+    return NM_OK;
+}
+
+extern "C" {
+
+int nm_net_create(unsigned long long seed, nm_net** out)
+{
+    if (!out) return NM_EINVAL;
+    nm_net* n = new nm_net();
+    long o = 0;
+    for (int l = 0; l < n->L; l++) {
+        n->off[l] = o;
+        o += layer_w(n, l) + n->cout[l];
+    }
+    n->off[4] = o;
+    n->nparam = o;
+    std::vector<float> h(o, 0.0f);
+    std::mt19937_64 rng(seed);
+    for (int l = 0; l < n->L; l++) {
+        // He-style uniform init scaled for the leaky ReLU; the last layer starts small
+        const float lim = (l == n->L - 1 ? 0.1f : 1.0f) * std::sqrt(6.0f / (27.0f * n->cin[l]));
+        std::uniform_real_distribution<float> U(-lim, lim);
+        for (long i = 0; i < layer_w(n, l); i++) h[n->off[l] + i] = U(rng);
+    }
+    int st = NM_OK;
+    st |= net_alloc((void**)&n->p, o * 4, nullptr);
+    st |= net_alloc((void**)&n->gr, o * 4, nullptr);
+    st |= net_alloc((void**)&n->m, o * 4, nullptr);
+    st |= net_alloc((void**)&n->v, o * 4, nullptr);
+    for (int l = 0; l < n->L; l++) {
+        st |= net_alloc((void**)&n->wf[l], 27 * 16 * n->cinp[l] * 2, nullptr);
+        st |= net_alloc((void**)&n->wb[l], 27 * 256 * 2, nullptr);
+    }
+    if (st != NM_OK || hipHostMalloc((void**)&n->hred, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+        nm_net_destroy(n);
+        return NM_ENOMEM;
+    }
+    if (hipMemcpy(n->p, h.data(), o * 4, hipMemcpyHostToDevice) != hipSuccess ||
+        hipMemset(n->m, 0, o * 4) != hipSuccess || hipMemset(n->v, 0, o * 4) != hipSuccess ||
+        hipMemset(n->gr, 0, o * 4) != hipSuccess || net_pack(n, nullptr) != NM_OK ||
+        hipDeviceSynchronize() != hipSuccess) {
+        nm_net_destroy(n);
+        return NM_EHIP;
+    }
+    *out = n;
+    return NM_OK;
+}
+
+void nm_net_destroy(nm_net* n)
+{
+    if (!n) return;
+    (void)hipDeviceSynchronize();
+    void* ptrs[] = {n->p, n->gr, n->m, n->v};
+    for (void* q : ptrs)
+        if (q) (void)hipFree(q);
+    for (int l = 0; l < 4; l++) {
+        if (n->wf[l]) (void)hipFree(n->wf[l]);
+        if (n->wb[l]) (void)hipFree(n->wb[l]);
+    }
+    for (void* q : n->ws_allocs) (void)hipFree(q);
+    if (n->hred) (void)hipHostFree(n->hred);
+    delete n;
+}
+
+long nm_net_num_params(const nm_net* n) { return n ? n->nparam : 0; }
+
+int nm_net_get_params(const nm_net* n, float* w)
+{
+    if (!n || !w) return NM_EINVAL;
+    return hipMemcpy(w, n->p, n->nparam * 4, hipMemcpyDeviceToHost) == hipSuccess ? NM_OK : NM_EHIP;
+}
+
+int nm_net_set_params(nm_net* n, const float* w)
+{
+    if (!n || !w) return NM_EINVAL;
+    if (hipMemcpy(n->p, w, n->nparam * 4, hipMemcpyHostToDevice) != hipSuccess) return NM_EHIP;
+    if (hipMemset(n->m, 0, n->nparam * 4) != hipSuccess || hipMemset(n->v, 0, n->nparam * 4) != hipSuccess)
+        return NM_EHIP;
+    n->step = 0;
+    if (net_pack(n, nullptr) != NM_OK) return NM_EHIP;
+    return hipDeviceSynchronize() == hipSuccess ? NM_OK : NM_EHIP;
+}
+
+static int check_grid(const int* n3)
+{
+    for (int i = 0; i < 3; i++)
+        if (n3[i] < 1 || n3[i] > 1024 || (n3[i] & (n3[i] - 1))) return NM_EUNSUPPORTED;
+    if (n3[0] < 16) return NM_EUNSUPPORTED;
+    return NM_OK;
+}
+
+// Forward pass: feat BF16 [N][32] -> pred FP32 [N][4] (device).  Uses the
+// network's workspace; pred_out may be NULL (then the internal buffer is kept).
+static int net_forward(nm_net* n, const Grid& g, const uint16_t* feat, hipStream_t s)
+{
+    CHECK_NM(net_workspace(n, g.N));
+    const uint16_t* in = feat;
+    for (int l = 0; l < n->L; l++) {
+        const float* b = n->p + n->off[l] + layer_w(n, l);
+        int e;
+        if (l < n->L - 1) e = launch_conv(n->cinp[l], EPI_BF16_ACT, in, n->wf[l], b, n->act[l + 1], nullptr, g, 16, 16, s);
+        else e = launch_conv(n->cinp[l], EPI_F32, in, n->wf[l], b, n->pred, nullptr, g, n->cout[l], kPredStride, s);
+        if (e) return e == -1 ? NM_EUNSUPPORTED : NM_EHIP;
+        in = n->act[l + 1];
+    }
+    return NM_OK;
+}
+
+int nm_net_forward(nm_net* n, void* stream, const int* grid, const void* feat_dev, void* pred_dev)
+{
+    if (!n || !grid || !feat_dev || !pred_dev) return NM_EINVAL;
+    CHECK_NM(check_grid(grid));
+    Grid g{grid[0], grid[1], grid[2], (long)grid[0] * grid[1] * grid[2]};
+    hipStream_t s = (hipStream_t)stream;
+    CHECK_NM(net_forward(n, g, (const uint16_t*)feat_dev, s));
+    if (hipMemcpyAsync(pred_dev, n->pred, g.N * kPredStride * 4, hipMemcpyDeviceToDevice, s) != hipSuccess)
+        return NM_EHIP;
+    return hipStreamSynchronize(s) == hipSuccess ? NM_OK : NM_EHIP;
+}
+
+int nm_net_train_step(nm_net* n, void* stream, const int* grid, const void* feat_dev, const void* target_dev,
+                      float lr, float* loss)
+{
+    if (!n || !grid || !feat_dev || !target_dev || !(lr > 0)) return NM_EINVAL;
+    CHECK_NM(check_grid(grid));
+    Grid g{grid[0], grid[1], grid[2], (long)grid[0] * grid[1] * grid[2]};
+    hipStream_t s = (hipStream_t)stream;
+    const uint16_t* feat = (const uint16_t*)feat_dev;
+    CHECK_NM(net_forward(n, g, feat, s));
+    // loss and dL/dpred
+    const int lb = 512;
+    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, n->pred, (const float*)target_dev, n->dz0, g.N, n->red);
+    // backward through the layers: dz0 holds dL/dZ_l
+    uint16_t *dz = n->dz0, *dznext = n->dz1;
+    for (int l = n->L - 1; l >= 0; l--) {
+        const uint16_t* in = l == 0 ? feat : n->act[l];
+        float* gW = n->gr + n->off[l];
+        float* gb = gW + layer_w(n, l);
+        if (launch_bwdw(n->cinp[l], in, dz, n->partial, gW, gb, n->cin[l], n->cout[l], g, s)) return NM_EHIP;
+        if (l > 0) {
+            // dZ_{l-1} = (W_l^T * dZ_l) . leaky'(A_{l-1}),  A_{l-1} = act[l]
+            if (launch_conv(16, EPI_BF16_DACT, dz, n->wb[l], nullptr, dznext, n->act[l], g, 16, 16, s))
+                return NM_EHIP;
+            std::swap(dz, dznext);
+        }
+    }
+    // Adam step and BF16 repack
+    n->step++;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->nparam + 255) / 256)), dim3(256), 0, s, n->p, n->gr, n->m, n->v,
+                       n->nparam, lr, b1, b2, eps, c1, c2);
+    if (net_pack(n, s) != NM_OK) return NM_EHIP;
+    if (loss) {
+        std::vector<double> part(lb);
+        if (hipMemcpyAsync(part.data(), n->red, lb * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return NM_EHIP;
+        if (hipStreamSynchronize(s) != hipSuccess) return NM_EHIP;
+        double t = 0;
+        for (int i = 0; i < lb; i++) t += part[i];
+        *loss = (float)t;
+    } else if (hipStreamSynchronize(s) != hipSuccess) {
+        return NM_EHIP;
+    }
+    return hipGetLastError() == hipSuccess ? NM_OK : NM_EHIP;
+}
+
+int nm_net_gradients(nm_net* n, void* stream, const int* grid, const void* feat_dev, const void* target_dev,
+                     float* grad_host, float* loss)
+{
+    // Same as one training step without the parameter update.
+    if (!n || !grid || !feat_dev || !target_dev || !grad_host) return NM_EINVAL;
+    CHECK_NM(check_grid(grid));
+    Grid g{grid[0], grid[1], grid[2], (long)grid[0] * grid[1] * grid[2]};
+    hipStream_t s = (hipStream_t)stream;
+    const uint16_t* feat = (const uint16_t*)feat_dev;
+    CHECK_NM(net_forward(n, g, feat, s));
+    const int lb = 512;
+    hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, n->pred, (const float*)target_dev, n->dz0, g.N, n->red);
+    uint16_t *dz = n->dz0, *dznext = n->dz1;
+    for (int l = n->L - 1; l >= 0; l--) {
+        const uint16_t* in = l == 0 ? feat : n->act[l];
+        float* gW = n->gr + n->off[l];
+        if (launch_bwdw(n->cinp[l], in, dz, n->partial, gW, gW + layer_w(n, l), n->cin[l], n->cout[l], g, s))
+            return NM_EHIP;
+        if (l > 0) {
+            if (launch_conv(16, EPI_BF16_DACT, dz, n->wb[l], nullptr, dznext, n->act[l], g, 16, 16, s))
+                return NM_EHIP;
+            std::swap(dz, dznext);
+        }
+    }
+    std::vector<double> part(lb);
+    if (hipMemcpyAsync(part.data(), n->red, lb * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(grad_host, n->gr, n->nparam * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return NM_EHIP;
+    if (loss) {
+        double t = 0;
+        for (int i = 0; i < lb; i++) t += part[i];
+        *loss = (float)t;
+    }
+    return NM_OK;
+}
+
+// Single-layer kernels on caller buffers (used to check each kernel against the oracle).
+int nm_conv3d_bf16(void* stream, int mode, const int* grid, int cinp, int cin, int cout, const void* x_dev,
+                   const void* w_fp32_host, const float* bias_host, const void* dy_dev, void* out_dev,
+                   float* dw_host, float* db_host)
+{
+    if (!grid || (cinp != 16 && cinp != 32) || cin > cinp || cout > 16 || cin < 1 || cout < 1) return NM_EINVAL;
+    CHECK_NM(check_grid(grid));
+    Grid g{grid[0], grid[1], grid[2], (long)grid[0] * grid[1] * grid[2]};
+    hipStream_t s = (hipStream_t)stream;
+    std::vector<void*> tmp;
+    float *wd = nullptr, *bd = nullptr, *part = nullptr, *dw = nullptr, *db = nullptr;
+    uint16_t *wf = nullptr, *wb = nullptr;
+    int rc = NM_OK;
+    const long nw = (long)cout * cin * 27;
+    if (net_alloc((void**)&wd, nw * 4, &tmp) || net_alloc((void**)&bd, 64, &tmp) ||
+        net_alloc((void**)&wf, 27 * 16 * cinp * 2, &tmp) || net_alloc((void**)&wb, 27 * 256 * 2, &tmp)) {
+        rc = NM_ENOMEM;
+        goto done;
+    }
+    if (w_fp32_host && hipMemcpy(wd, w_fp32_host, nw * 4, hipMemcpyHostToDevice) != hipSuccess) rc = NM_EHIP;
+    (void)hipMemset(bd, 0, 64);
+    if (bias_host && hipMemcpy(bd, bias_host, cout * 4, hipMemcpyHostToDevice) != hipSuccess) rc = NM_EHIP;
+    if (rc) goto done;
+    {
+        const int tot = 27 * 16 * cinp > 27 * 256 ? 27 * 16 * cinp : 27 * 256;
+        hipLaunchKernelGGL(k_pack, dim3((tot + 255) / 256), dim3(256), 0, s, wd, cin, cout, cinp, wf,
+                           cinp == 16 ? wb : nullptr);
+    }
+    if (mode == 0) {
+        // forward, FP32 output [N][16] without activation
+        if (launch_conv(cinp, EPI_F32, (const uint16_t*)x_dev, wf, bd, out_dev, nullptr, g, cout, 16, s)) rc = NM_EHIP;
+    } else if (mode == 1) {
+        // backward data: out = W^T * dy as FP32 [N][16] (dy BF16 [N][16])
+        if (cinp != 16) rc = NM_EINVAL;
+        else if (launch_conv(16, EPI_F32, (const uint16_t*)dy_dev, wb, nullptr, out_dev, nullptr, g, cin, 16, s))
+            rc = NM_EHIP;
+    } else if (mode == 2) {
+        const long waves = bwdw_waves(g.N / 16);
+        if (net_alloc((void**)&part, waves * (27L * 2 * 256 + 64) * 4, &tmp) || net_alloc((void**)&dw, nw * 4, &tmp) ||
+            net_alloc((void**)&db, 64, &tmp)) {
+            rc = NM_ENOMEM;
+            goto done;
+        }
+        if (launch_bwdw(cinp, (const uint16_t*)x_dev, (const uint16_t*)dy_dev, part, dw, db, cin, cout, g, s))
+            rc = NM_EHIP;
+        else if (hipMemcpyAsync(dw_host, dw, nw * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                 hipMemcpyAsync(db_host, db, cout * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+            rc = NM_EHIP;
+    } else {
+        rc = NM_EINVAL;
+    }
+    if (hipStreamSynchronize(s) != hipSuccess && rc == NM_OK) rc = NM_EHIP;
+done:
+    for (void* q : tmp) (void)hipFree(q);
+    return rc;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------
+// Solver-side helpers (called from nm_api.hip)
+// ---------------------------------------------------------------------------
+namespace nm {
+
+int warm_features(const WarmArgs& a, hipStream_t s)
+{
+    const long n = 3 * a.N;
+    const int nb = 512;
+    hipLaunchKernelGGL(k_incr_norm, dim3(nb), dim3(256), 0, s, a.ut, a.u, n, a.red);
+    hipLaunchKernelGGL(k_sum_scale, dim3(1), dim3(64), 0, s, a.red, nb, n, a.scale);
+    hipLaunchKernelGGL(k_features, dim3(2048), dim3(256), 0, s, a.u, a.v, a.a, a.dt, a.c2, a.phase, a.matf, a.N,
+                       a.scale, a.feat);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
+{
+    Grid g{a.n1, a.n2, a.n3, a.N};
+    int n3[3] = {a.n1, a.n2, a.n3};
+    if (check_grid(n3) != NM_OK) return -1;
+    if (warm_features(a, s)) return -2;
+    if (net_forward(net, g, a.feat, s) != NM_OK) return -2;
+    hipLaunchKernelGGL(k_predict, dim3(2048), dim3(256), 0, s, a.ut, net->pred, a.scale, x0, a.N);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int warm_target(const WarmArgs& a, const double* unext, float* target, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_target, dim3(2048), dim3(256), 0, s, unext, a.ut, a.scale, target, a.N);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+} // namespace nm

@@ -24,6 +24,9 @@ WS_COLD, WS_PREV, WS_TAYLOR, WS_LEARNED = 0, 1, 2, 3
 
 EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_precond_apply", "nm_pcg_solve",
             "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream", "nm_profile_passes",
+            "nm_net_create", "nm_net_destroy", "nm_net_num_params", "nm_net_get_params", "nm_net_set_params",
+            "nm_net_forward", "nm_net_train_step", "nm_net_gradients", "nm_conv3d_bf16", "nm_ws_attach",
+            "nm_ws_features", "nm_ws_target",
             "nm_last_error", "nm_destroy")
 
 
@@ -78,6 +81,20 @@ def load_library():
     L.nm_state_device_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
     L.nm_green_matrix.argtypes = [vp, vp]
     L.nm_profile_passes.argtypes = [vp, i, vp, vp, i, i, C.POINTER(C.c_double)]
+    L.nm_net_create.argtypes = [C.c_ulonglong, C.POINTER(vp)]
+    L.nm_net_destroy.argtypes = [vp]
+    L.nm_net_destroy.restype = None
+    L.nm_net_num_params.argtypes = [vp]
+    L.nm_net_num_params.restype = C.c_long
+    L.nm_net_get_params.argtypes = [vp, vp]
+    L.nm_net_set_params.argtypes = [vp, vp]
+    L.nm_net_forward.argtypes = [vp, vp, vp, vp, vp]
+    L.nm_net_train_step.argtypes = [vp, vp, vp, vp, vp, C.c_float, C.POINTER(C.c_float)]
+    L.nm_net_gradients.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_float)]
+    L.nm_conv3d_bf16.argtypes = [vp, i, vp, i, i, i, vp, vp, vp, vp, vp, vp, vp]
+    L.nm_ws_attach.argtypes = [vp, vp]
+    L.nm_ws_features.argtypes = [vp, vp]
+    L.nm_ws_target.argtypes = [vp, vp]
     L.nm_get_stream.argtypes = [vp]
     L.nm_get_stream.restype = vp
     L.nm_last_error.argtypes = [vp]
@@ -281,3 +298,105 @@ def profile_passes(ctx: Context, which: int, u, out, reps: int = 10):
 
 def get_stream(ctx: Context) -> int:
     return load_library().nm_get_stream(ctx.handle) or 0
+
+
+# --------------------------------------------------------------------------------------------
+# Learned warm start
+# --------------------------------------------------------------------------------------------
+def _grid(n):
+    return (C.c_int * 3)(*[int(x) for x in n])
+
+
+def _stream_arg(stream):
+    return None if stream is None else C.c_void_p(int(stream))
+
+
+class Net:
+    """The warm-start network (nm_net_*).  Device buffers are torch tensors."""
+
+    def __init__(self, seed: int = 0):
+        lib = load_library()
+        out = C.c_void_p()
+        code = lib.nm_net_create(int(seed), C.byref(out))
+        if code != NM_OK:
+            raise NewmarkError(code, "nm_net_create failed")
+        self._ptr = out.value
+
+    @property
+    def handle(self):
+        if not self._ptr:
+            raise RuntimeError("network is closed")
+        return self._ptr
+
+    def close(self):
+        if self._ptr:
+            load_library().nm_net_destroy(self._ptr)
+            self._ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def num_params(self) -> int:
+        return int(load_library().nm_net_num_params(self.handle))
+
+    def get_params(self) -> np.ndarray:
+        w = np.empty(self.num_params(), dtype=np.float32)
+        _chk(load_library().nm_net_get_params(self.handle, w.ctypes.data), "get_params")
+        return w
+
+    def set_params(self, w) -> None:
+        w = np.ascontiguousarray(w, dtype=np.float32)
+        assert w.size == self.num_params()
+        _chk(load_library().nm_net_set_params(self.handle, w.ctypes.data), "set_params")
+
+    def forward(self, grid, feat, pred, stream=None) -> None:
+        _chk(load_library().nm_net_forward(self.handle, _stream_arg(stream), _grid(grid), feat.data_ptr(),
+                                           pred.data_ptr()), "forward")
+
+    def train_step(self, grid, feat, target, lr: float, stream=None) -> float:
+        loss = C.c_float(0)
+        _chk(load_library().nm_net_train_step(self.handle, _stream_arg(stream), _grid(grid), feat.data_ptr(),
+                                              target.data_ptr(), float(lr), C.byref(loss)), "train_step")
+        return float(loss.value)
+
+    def gradients(self, grid, feat, target, stream=None):
+        g = np.empty(self.num_params(), dtype=np.float32)
+        loss = C.c_float(0)
+        _chk(load_library().nm_net_gradients(self.handle, _stream_arg(stream), _grid(grid), feat.data_ptr(),
+                                             target.data_ptr(), g.ctypes.data, C.byref(loss)), "gradients")
+        return g, float(loss.value)
+
+
+def _chk(code, what):
+    if code != NM_OK:
+        raise NewmarkError(code, what)
+
+
+def conv3d_bf16(mode, grid, cinp, cin, cout, x=None, w=None, bias=None, dy=None, out=None, stream=None):
+    """One network layer's kernel on caller buffers (see nm_conv3d_bf16)."""
+    wa = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
+    ba = None if bias is None else np.ascontiguousarray(bias, dtype=np.float32)
+    dw = np.zeros((cout, cin, 27), dtype=np.float32)
+    db = np.zeros(cout, dtype=np.float32)
+    _chk(load_library().nm_conv3d_bf16(_stream_arg(stream), int(mode), _grid(grid), int(cinp), int(cin), int(cout),
+                                       None if x is None else x.data_ptr(), None if wa is None else wa.ctypes.data,
+                                       None if ba is None else ba.ctypes.data, None if dy is None else dy.data_ptr(),
+                                       None if out is None else out.data_ptr(), dw.ctypes.data, db.ctypes.data),
+         "conv3d_bf16")
+    return dw, db
+
+
+def ws_attach(ctx: Context, net) -> None:
+    ctx.check(load_library().nm_ws_attach(ctx.handle, None if net is None else net.handle))
+    ctx._net = net
+
+
+def ws_features(ctx: Context, feat=None) -> None:
+    ctx.check(load_library().nm_ws_features(ctx.handle, None if feat is None else feat.data_ptr()))
+
+
+def ws_target(ctx: Context, target) -> None:
+    ctx.check(load_library().nm_ws_target(ctx.handle, target.data_ptr()))

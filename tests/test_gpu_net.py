@@ -1,0 +1,250 @@
+"""GPU checks of the learned-warm-start network against the FP64 oracle.
+
+Each matrix-core kernel is compared with the oracle's direct convolution on
+identical BF16-valued inputs and weights (the GPU accumulates in FP32, so the
+bar is a few FP32 rounding errors of the 27 * Cin-term sums).  The whole
+network gradient is compared with a reference that runs the oracle's
+convolutions in FP64 and rounds activations and activation gradients to BF16
+at the same points as the GPU (bar 1e-2 relative L2: a BF16 rounding can fall
+on the other side for a few entries).  Training must lower the loss, and the
+learned initial iterate must leave the converged solution unchanged.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2211_08263_amd import newmark as nmb
+from paper_2211_08263_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+LEAK = 0.1
+
+
+def bf16_bits(a):
+    u = np.ascontiguousarray(a, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = u + 0x7FFF + ((u >> 16) & 1)
+    return (u >> 16).astype(np.uint16)
+
+
+def bf16_val(a):
+    return (bf16_bits(a).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def dev_u16(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a).view(np.int16)).cuda()
+
+
+def cl_to_cf(x, n, c):
+    """channels-last [N][C] -> channels-first (c, n3, n2, n1)"""
+    return np.ascontiguousarray(x[:, :c].T).reshape(c, n[2], n[1], n[0])
+
+
+def cf_to_cl(x):
+    c = x.shape[0]
+    return np.ascontiguousarray(x.reshape(c, -1).T)
+
+
+GRIDS = [(16, 8, 8), (32, 16, 8), (16, 16, 32)]
+
+
+@pytest.mark.parametrize("n", GRIDS)
+@pytest.mark.parametrize("cinp,cin,cout", [(32, 31, 16), (16, 16, 16), (16, 16, 3)])
+def test_conv_forward_matches_oracle(n, cinp, cin, cout):
+    import torch
+    rng = np.random.default_rng(sum(n) + cin + cout)
+    N = n[0] * n[1] * n[2]
+    x = bf16_val(rng.standard_normal((N, cinp)))
+    w = rng.standard_normal((cout, cin, 27)).astype(np.float32) * 0.3
+    b = rng.standard_normal(cout).astype(np.float32)
+    out = torch.zeros(N * 16, dtype=torch.float32, device="cuda")
+    nmb.conv3d_bf16(0, n, cinp, cin, cout, x=dev_u16(bf16_bits(x)), w=w, bias=b, out=out)
+    got = out.cpu().numpy().reshape(N, 16)[:, :cout]
+    want = cf_to_cl(oracle.conv3d_fwd(cl_to_cf(x, n, cin), bf16_val(w).reshape(cout, cin, 3, 3, 3), b, n))
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"conv fwd n={n} cinp={cinp} cin={cin} cout={cout}: {err:.2e}", flush=True)
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("n", GRIDS)
+@pytest.mark.parametrize("cout", [16, 3])
+def test_conv_backward_data_matches_oracle(n, cout):
+    import torch
+    rng = np.random.default_rng(7 + cout)
+    N = n[0] * n[1] * n[2]
+    cin = 16
+    dy = np.zeros((N, 16))
+    dy[:, :cout] = bf16_val(rng.standard_normal((N, cout)))
+    w = rng.standard_normal((cout, cin, 27)).astype(np.float32) * 0.3
+    out = torch.zeros(N * 16, dtype=torch.float32, device="cuda")
+    nmb.conv3d_bf16(1, n, 16, cin, cout, w=w, dy=dev_u16(bf16_bits(dy)), out=out)
+    got = out.cpu().numpy().reshape(N, 16)[:, :cin]
+    want = cf_to_cl(oracle.conv3d_bwd_data(cl_to_cf(dy, n, cout), bf16_val(w).reshape(cout, cin, 3, 3, 3), n))
+    err = np.abs(got - want).max() / np.abs(want).max()
+    print(f"conv bwd-data n={n} cout={cout}: {err:.2e}", flush=True)
+    assert err < 1e-5
+
+
+@pytest.mark.parametrize("n", GRIDS)
+@pytest.mark.parametrize("cinp,cin,cout", [(32, 31, 16), (16, 16, 3)])
+def test_conv_backward_weight_matches_oracle(n, cinp, cin, cout):
+    rng = np.random.default_rng(11 + cin)
+    N = n[0] * n[1] * n[2]
+    x = bf16_val(rng.standard_normal((N, cinp)))
+    dy = np.zeros((N, 16))
+    dy[:, :cout] = bf16_val(rng.standard_normal((N, cout)))
+    dw, db = nmb.conv3d_bf16(2, n, cinp, cin, cout, x=dev_u16(bf16_bits(x)), dy=dev_u16(bf16_bits(dy)))
+    wdw, wdb = oracle.conv3d_bwd_weight(cl_to_cf(x, n, cin), cl_to_cf(dy, n, cout), cin, cout, n)
+    err = np.abs(dw - wdw.reshape(cout, cin, 27)).max() / np.abs(wdw).max()
+    errb = np.abs(db - wdb).max() / np.abs(wdb).max()
+    print(f"conv bwd-weight n={n} cin={cin} cout={cout}: {err:.2e} bias {errb:.2e}", flush=True)
+    assert err < 1e-4 and errb < 1e-4
+
+
+def _reference_grad(params, feat, target, n):
+    """FP64 backprop with BF16 storage of activations and activation gradients."""
+    cins, couts = [31, 16, 16, 16], [16, 16, 16, 3]
+    Ws, bs, off = [], [], 0
+    for ci, co in zip(cins, couts):
+        Ws.append(bf16_val(params[off: off + co * ci * 27]).reshape(co, ci, 3, 3, 3))
+        off += co * ci * 27
+        bs.append(params[off: off + co].astype(np.float64))
+        off += co
+    N = feat.shape[0]
+    A = [cl_to_cf(feat, n, 31)]
+    for l in range(3):
+        z = oracle.conv3d_fwd(A[-1], Ws[l], bs[l], n)
+        A.append(bf16_val(np.where(z > 0, z, LEAK * z)))
+    pred = oracle.conv3d_fwd(A[3], Ws[3], bs[3], n)
+    t = cl_to_cf(target, n, 3)
+    loss = np.mean((pred - t) ** 2)
+    dz = bf16_val(2 * (pred - t) / (3 * N))
+    grads = [None] * 4
+    for l in range(3, -1, -1):
+        dw, db = oracle.conv3d_bwd_weight(A[l], dz, cins[l], couts[l], n)
+        grads[l] = (dw.reshape(-1), db)
+        if l > 0:
+            da = oracle.conv3d_bwd_data(dz, Ws[l], n)
+            dz = bf16_val(np.where(A[l] > 0, da, LEAK * da))
+    g = np.concatenate([np.concatenate([gw, gb]) for gw, gb in grads])
+    return g, loss
+
+
+def test_network_gradient_matches_reference():
+    import torch
+    n = (16, 16, 8)
+    N = n[0] * n[1] * n[2]
+    rng = np.random.default_rng(3)
+    feat = np.zeros((N, 32))
+    feat[:, :31] = bf16_val(rng.standard_normal((N, 31)))
+    target = np.zeros((N, 4), dtype=np.float32)
+    target[:, :3] = rng.standard_normal((N, 3))
+    net = nmb.Net(seed=5)
+    params = net.get_params()
+    g, loss = net.gradients(n, dev_u16(bf16_bits(feat)), torch.from_numpy(target).cuda())
+    gr, lr = _reference_grad(params, feat, target, n)
+    err = np.linalg.norm(g - gr) / np.linalg.norm(gr)
+    print(f"network gradient rel L2 {err:.2e}, loss {loss:.6f} vs {lr:.6f}", flush=True)
+    assert abs(loss - lr) / lr < 1e-4
+    assert err < 1e-2
+    net.close()
+
+
+def _trajectory_samples(pb, steps, net):
+    """Features/targets of consecutive steps of the FP64 solver (previous-step start)."""
+    import torch
+    N = pb.n_vox
+    feats, targets = [], []
+    with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10, max_iter=500)) as ctx:
+        nmb.ws_attach(ctx, net)
+        for s in range(steps):
+            f = torch.empty(N * 32, dtype=torch.int16, device="cuda")
+            t = torch.empty(N * 4, dtype=torch.float32, device="cuda")
+            nmb.ws_features(ctx, f)
+            nmb.newmark_step(ctx, pb.U(s + 1))
+            nmb.ws_target(ctx, t)
+            feats.append(f)
+            targets.append(t)
+    return feats, targets
+
+
+def test_training_lowers_loss_and_learned_start_keeps_the_solution():
+    import torch
+    pb = W.make_polycrystal(n=32, n_grains=8, seed=1001, n_steps=16)
+    net = nmb.Net(seed=1)
+    feats, targets = _trajectory_samples(pb, 16, net)
+    grid = pb.n
+    losses = []
+    for epoch in range(25):
+        tot = 0.0
+        for f, t in zip(feats[4:], targets[4:]):
+            tot += net.train_step(grid, f, t, lr=2e-3)
+        losses.append(tot / len(feats[4:]))
+    print("training losses", [f"{x:.4g}" for x in losses[::4]], flush=True)
+    assert losses[-1] < 0.7 * losses[0]
+    # learned initial iterate: same converged trajectory as the previous-step start
+    res = {}
+    for ws in (nmb.WS_PREV, nmb.WS_LEARNED):
+        with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10, max_iter=500, warm_start=ws)) as ctx:
+            if ws == nmb.WS_LEARNED:
+                nmb.ws_attach(ctx, net)
+            its = []
+            for s in range(12):
+                st = nmb.newmark_step(ctx, pb.U(s + 1))
+                its.append(st["iters"][0])
+            res[ws] = (nmb.get_state(ctx)["u"], its)
+    u0, u1 = res[nmb.WS_PREV][0], res[nmb.WS_LEARNED][0]
+    rel = np.linalg.norm(u1 - u0) / np.linalg.norm(u0)
+    print("iterations prev", res[nmb.WS_PREV][1], "learned", res[nmb.WS_LEARNED][1], "rel diff", rel, flush=True)
+    assert rel < 1e-7
+    net.close()
+
+
+def test_features_and_target_match_the_newmark_state():
+    """Features from (u_n, v_n, a_n), scale s = rms(u~ - u_n) and target (u_{n+1} - u~)/s,
+    recomputed in FP64 from the library's own state (the predictor u~ written out from the
+    Newmark update rule with beta = 1/4)."""
+    import torch
+    pb = W.make_polycrystal(n=16, n_grains=4, seed=1002, n_steps=8)
+    N = pb.n_vox
+    net = nmb.Net(seed=2)
+    with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10, max_iter=500)) as ctx:
+        nmb.ws_attach(ctx, net)
+        for s in range(5):
+            nmb.newmark_step(ctx, pb.U(s + 1))
+        st = nmb.get_state(ctx)
+        f = torch.empty(N * 32, dtype=torch.int16, device="cuda")
+        t = torch.empty(N * 4, dtype=torch.float32, device="cuda")
+        nmb.ws_features(ctx, f)
+        nmb.newmark_step(ctx, pb.U(6))
+        nmb.ws_target(ctx, t)
+        u1 = nmb.get_state(ctx)["u"]
+    net.close()
+    u, v, a = (st[k].reshape(3, N) for k in ("u", "v", "a"))
+    c2 = pb.dt ** 2 * (0.5 - pb.beta)
+    ut = u + pb.dt * v + c2 * a
+    s = np.sqrt(np.mean((ut - u) ** 2))
+    assert s > 0
+    feat = (f.cpu().numpy().view(np.uint16).astype(np.uint32) << 16).view(np.float32).reshape(N, 32)
+    want = np.concatenate([u / s, pb.dt * v / s, c2 * a / s]).T
+    err = np.abs(feat[:, :9] - want).max() / np.abs(want).max()
+    print(f"state features: max err {err:.2e} (BF16 half-ulp 3.9e-3)", flush=True)
+    assert err < 4e-3
+    ph = pb.phase_id.reshape(-1)
+    mat = feat[:, 9:31].astype(np.float64)
+    ref = np.concatenate([pb.rho[:, None], pb.C21], axis=1)[ph]
+    # density over one constant, the 21 stiffnesses over one other constant (C11 of the
+    # reference medium), each rounded to BF16
+    for sl in (slice(0, 1), slice(1, 22)):
+        m, r = mat[:, sl], ref[:, sl]
+        k = float((m * r).sum() / (r * r).sum())
+        assert k > 0
+        dev = np.abs(m - k * r).max() / np.abs(k * r).max()
+        assert dev < 4e-3, (sl, dev)
+    assert feat[:, 31].max() == 0 and feat[:, 31].min() == 0
+    tg = t.cpu().numpy().reshape(N, 4)
+    wt = ((u1.reshape(3, N) - ut) / s).T
+    errt = np.abs(tg[:, :3] - wt).max() / np.abs(wt).max()
+    print(f"target: max err {errt:.2e}", flush=True)
+    assert errt < 1e-6 and tg[:, 3].max() == 0 and tg[:, 3].min() == 0
