@@ -37,6 +37,29 @@ OPERATOR_PASS_FIELDS = {"x_fwd": 6, "y_deriv": 6, "z_strain": 12, "x_stress": 12
 OPERATOR_PASS_ID_BYTES = {"x_stress": 2, "x_inv_inertia": 2}
 
 
+# HBM bytes per dispatch of the FP64 x_stress pass at 256^3 from two rocprofv3 counter
+# runs (profiles/hbm_traffic_256cube.md): FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the
+# factors a 512 MiB device copy reads for those counters.  Valid only for the kernel
+# sources they were taken on (hash below); otherwise the traffic is reported as null.
+PMC_TRAFFIC = {"kernel": "x_stress", "n": 256, "fetch_kib": 411527.2, "write_kib": 786432.0,
+               "fetch_scale": 2.000, "write_scale": 1.000, "sources_sha256_16": "3616c8c8285eb01d"}
+PMC_SOURCES = ("nm_common.h", "nm_fft.h", "nm_passes.h", "nm_passes.hip")
+
+
+def pmc_traffic(kernel, n):
+    import hashlib
+    t = PMC_TRAFFIC
+    if kernel != t["kernel"] or n != t["n"]:
+        return None
+    h = hashlib.sha256()
+    for f in PMC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2211_08263_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    if h.hexdigest()[:16] != t["sources_sha256_16"]:
+        return None
+    return round(1024 * (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]))
+
+
 def pass_bytes_per_voxel(name, real_bytes):
     return OPERATOR_PASS_FIELDS[name] * real_bytes + OPERATOR_PASS_ID_BYTES.get(name, 0)
 
@@ -45,7 +68,7 @@ def operator_bytes_per_voxel(real_bytes):
     return sum(pass_bytes_per_voxel(k, real_bytes) for k in OPERATOR_PASS_FIELDS)
 
 
-def run_variant(pb, opts, steps, warmup, label):
+def run_variant(pb, opts, steps, warmup, label, net=None):
     import torch
     from paper_2211_08263_amd import newmark as nmb
     t0 = time.time()
@@ -53,6 +76,8 @@ def run_variant(pb, opts, steps, warmup, label):
     log(f"[{label}] init {time.time() - t0:.1f}s")
     stats = []
     try:
+        if net is not None:
+            nmb.ws_attach(ctx, net)
         for s in range(warmup):
             nmb.newmark_step(ctx, pb.U(s + 1))
         torch.cuda.synchronize()
@@ -66,9 +91,12 @@ def run_variant(pb, opts, steps, warmup, label):
     its = [st["iters"][0] for st in stats]
     inner = [st["inner_iters"] for st in stats]
     sweeps = [st["sweeps"] for st in stats]
-    log(f"[{label}] {steps} steps in {dt:.3f}s -> {steps / dt:.3f} steps/s; iters {its} inner {inner}")
+    r0 = [round(st["relres0"], 4) for st in stats]
+    log(f"[{label}] {steps} steps in {dt:.3f}s -> {steps / dt:.3f} steps/s; iters {its} inner {inner} "
+        f"initial relres {r0}")
     return {"steps_per_s": steps / dt, "ms_per_step": 1e3 * dt / steps, "iters_per_step": its,
-            "inner_iters_per_step": inner, "sweeps_per_step": sweeps,
+            "inner_iters_per_step": inner, "sweeps_per_step": sweeps, "initial_relres_per_step": r0,
+            "warm_start_ms_mean": sum(st["t_warm_ms"] for st in stats) / len(stats),
             "relres_max": max(st["relres"] for st in stats)}
 
 
@@ -112,25 +140,36 @@ def operator_rates(pb):
     return out
 
 
-def cpu_baseline(pb, iters_per_step):
-    """The FP64 oracle (single thread) timed on one operator apply of this workload."""
-    import numpy as np
+def cpu_baseline(n_full, grains_full, seed, iters_per_step, n_sample=128):
+    """The FP64 oracle (single thread) timed on one operator apply and one preconditioner
+    apply of a smaller polycrystal with the same grain density, scaled to the full grid by
+    N log N (both are FFT-bound), and combined into a per-step time."""
     import oracle
     from paper_2211_08263_amd import workloads as W
+    g = max(1, round(grains_full * (n_sample / n_full) ** 3))
+    pb = W.make_polycrystal(n=n_sample, n_grains=g, seed=seed)
     op = oracle.OracleProblem.from_problem(pb)
     u = W.random_field(op.field_shape, seed=7)
-    log("[cpu] oracle operator apply on the full grid ...")
+    log(f"[cpu] oracle operator and preconditioner apply on {n_sample}^3 ...")
     t0 = time.perf_counter()
     op.apply(u)
     t_apply = time.perf_counter() - t0
-    applies = iters_per_step + 2  # PCG iterations + initial residual + reference norm
-    step_s = applies * t_apply
-    log(f"[cpu] one apply {t_apply:.1f}s -> >= {step_s:.0f}s per step")
+    t0 = time.perf_counter()
+    op.precond(u)
+    t_prec = time.perf_counter() - t0
+    N_s, N_f = n_sample ** 3, n_full ** 3
+    scale = (N_f * math.log2(N_f)) / (N_s * math.log2(N_s))
+    applies, precs = iters_per_step + 2, iters_per_step + 1
+    step_s = scale * (applies * t_apply + precs * t_prec)
+    log(f"[cpu] apply {t_apply:.2f}s precond {t_prec:.2f}s at {n_sample}^3 -> {step_s:.0f}s per {n_full}^3 step")
     return {"value": 1.0 / step_s, "unit": "steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one FP64 oracle operator apply on the {pb.n[0]}^3 workload ({t_apply:.1f} s, 1 thread); "
-                       f"per-step time = {applies} applies (mean PCG iterations per FP64 GPU step + 2), "
-                       "preconditioner and vector work excluded, so this is an upper bound on the oracle rate"),
-            "apply_s": t_apply, "gvoxel_per_s": pb.n_vox / t_apply / 1e9}
+            "sample": (f"one FP64 oracle operator apply ({t_apply:.2f} s) and one preconditioner apply "
+                       f"({t_prec:.2f} s) on a {n_sample}^3 polycrystal with {g} grains (same grain density), "
+                       f"1 thread, scaled by N log N (x{scale:.2f}) to {n_full}^3; per step {applies} applies + "
+                       f"{precs} preconditioner applies (mean FP64 PCG iterations {iters_per_step}); vector "
+                       "updates excluded"),
+            "apply_s_sample": t_apply, "precond_s_sample": t_prec,
+            "gvoxel_per_s_apply": N_s / t_apply / 1e9}
 
 
 def main():
@@ -141,7 +180,9 @@ def main():
     ap.add_argument("--n", type=int, default=256)
     ap.add_argument("--grains", type=int, default=500)
     ap.add_argument("--seed", type=int, default=3)
-    ap.add_argument("--variants", default="fp64,mixed")
+    ap.add_argument("--variants", default="fp64,fp64_cold,mixed,mixed_cold,mixed_learned",
+                    help="precision (fp64|mixed) _ initial iterate (prev|cold|taylor|learned; default prev)")
+    ap.add_argument("--inner-tol", type=float, default=1e-5, help="floor of the FP32 inner-solve tolerance")
     ap.add_argument("--cpu-sample", choices=["apply", "none"], default="apply")
     ap.add_argument("--skip-operator", action="store_true")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -171,17 +212,26 @@ def main():
         f"dt {pb.dt:.4f}, fc {pb.pulse_fc:.4f}, |Gamma| {pb.gamma_idx.size}")
 
     variants = {}
-    starts = {"prev": nmb.WS_PREV, "cold": nmb.WS_COLD, "taylor": nmb.WS_TAYLOR}
-    for v in args.variants.split(","):
+    starts = {"prev": nmb.WS_PREV, "cold": nmb.WS_COLD, "taylor": nmb.WS_TAYLOR, "learned": nmb.WS_LEARNED}
+    names = args.variants.split(",")
+    for v in names:
         prec, _, start = v.partition("_")
         if prec not in ("fp64", "mixed") or (start and start not in starts):
             raise SystemExit(f"unknown variant {v}")
+    net = None
+    if any(v.endswith("_learned") for v in names):
+        from paper_2211_08263_amd import warmstart
+        net = nmb.Net()
+        if not warmstart.load_weights(net):
+            raise SystemExit(f"no trained warm-start weights at {warmstart.DEFAULT_WEIGHTS}")
+    for v in names:
+        prec, _, start = v.partition("_")
         o = nmb.Options(tol=1e-8, max_iter=500, warm_start=starts[start or "prev"],
-                        precision=nmb.PREC_MIXED if prec == "mixed" else nmb.PREC_FP64, inner_tol=1e-4)
-        variants[v] = run_variant(pb, o, args.steps, args.warmup, v)
+                        precision=nmb.PREC_MIXED if prec == "mixed" else nmb.PREC_FP64, inner_tol=args.inner_tol)
+        variants[v] = run_variant(pb, o, args.steps, args.warmup, v, net if start == "learned" else None)
 
     op = {} if args.skip_operator else operator_rates(pb)
-    head = "mixed" if "mixed" in variants else next(iter(variants))
+    head = next((h for h in ("mixed_learned", "mixed") if h in variants), names[0])
     hv = variants[head]
     roof = None
     if op:
@@ -191,21 +241,26 @@ def main():
         achieved = bpv * pb.n_vox / (passes[dom] * 1e-3) / 1e9
         roof = {"bound": "hbm", "kernel": f"{dom} (fp64 operator pass)", "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "bytes_per_voxel": bpv, "avg_ms": passes[dom],
+                "traffic": pmc_traffic(dom, args.n), "traffic_unit": "bytes per launch",
+                "algorithmic_bytes": bpv * pb.n_vox, "bytes_per_voxel": bpv, "avg_ms": passes[dom],
                 "operator_chain_GBps_fp64": round(op["fp64"]["model_GBps"], 1),
                 "operator_chain_frac_fp64": round(op["fp64"]["model_GBps"] / HBM_PEAK_GBS, 4)}
     cpu = None
     if args.cpu_sample == "apply":
         fp = variants.get("fp64", hv)
-        cpu = cpu_baseline(pb, int(round(float(np.mean(fp["iters_per_step"])))))
+        cpu = cpu_baseline(args.n, args.grains, args.seed, int(round(float(np.mean(fp["iters_per_step"])))))
     line = {
         "metric": METRIC, "value": round(hv["steps_per_s"], 4), "unit": "steps/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(hv["ms_per_step"], 3),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f32+f64" if head == "mixed" else "f64", "data": "synthetic",
+        "dtype": ("bf16+f32+f64" if head.endswith("learned") else "f32+f64") if head.startswith("mixed") else "f64", "data": "synthetic",
         "config": {"workload": f"{args.n}^3 Cu polycrystal, {args.grains} Voronoi grains (seed {args.seed}), "
                                "x=0 slab Ricker, tol 1e-8, projected Gamma route",
-                   "headline_variant": head, "grid": [args.n] * 3, "dt": pb.dt, "tol": 1e-8,
+                   "baseline_variant": "fp64 (FP64 PCG, previous-step initial iterate)",
+                   "headline_variant": head,
+                   "speedup_vs_fp64": (round(hv["steps_per_s"] / variants["fp64"]["steps_per_s"], 3)
+                                       if "fp64" in variants else None), "grid": [args.n] * 3, "dt": pb.dt, "tol": 1e-8,
+                   "inner_tol_floor": args.inner_tol,
                    "variants": variants,
                    "operator": op},
         "roofline": roof, "cpu_baseline": cpu,

@@ -78,7 +78,9 @@ typedef struct nm_options {
     int route;                /* nm_route: GREEN (paper, G matrix + LU) or PROJECTED (PCG on the free dofs) */
     double tol;               /* relative residual tolerance of each solve */
     int max_iter;             /* per solve (per inner solve in mixed precision) */
-    double inner_tol;         /* mixed precision: relative tolerance of each FP32 inner solve */
+    double inner_tol;         /* mixed precision: smallest relative tolerance asked of an FP32 inner
+                                 solve (each solve reduces its residual by max(inner_tol, half the
+                                 factor the outer tolerance still needs)); <= 0 means 1e-5 */
     int max_sweeps;           /* mixed precision: maximum refinement sweeps per step */
     int warm_start;           /* nm_warm_start */
     double green_tol;         /* tolerance of the unit-force solves that build G */
@@ -91,6 +93,7 @@ typedef struct nm_step_stats {
     int sweeps;               /* mixed precision: FP64 refinement sweeps */
     int inner_iters;          /* mixed precision: total FP32 PCG iterations */
     double relres;            /* final relative residual (true residual when measured, else recursive) */
+    double relres0;           /* relative residual of the initial guess (first solve) */
     double t_step_ms;         /* wall time of the step (host clock, after a stream synchronize) */
     double t_warm_ms;         /* wall time of the warm-start prediction */
 } nm_step_stats;

@@ -236,6 +236,7 @@ template <typename T> int norm2(nm_ctx* c, const T* x, double* out)
 struct PcgResult {
     int iters = 0;
     double rr = 0;
+    double rr0 = 0;
     bool converged = false;
 };
 
@@ -258,6 +259,7 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
     double rr = c->hscal[S_RR];
     res->iters = 0;
     res->rr = rr;
+    res->rr0 = rr;
     if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite initial residual");
     if (bref <= 0) bref = 1.0;
     const double thr = tol * bref;
@@ -351,6 +353,7 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st)
         LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
         CHK(read_scalars(c));
         rr = c->hscal[S_RR];
+        if (sweeps == 0 && st) st->relres0 = std::sqrt(rr) / bref;
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual in refinement sweep %d", sweeps);
         if (std::sqrt(rr) <= c->opt.tol * bref) break;
         if (sweeps >= c->opt.max_sweeps)
@@ -359,8 +362,11 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st)
         LCHK(c, launch_cast_d2f(c->rhs32, c->r, n, s));
         LCHK(c, launch_fill<float>(c->d32, 0.0f, n, s));
         PcgResult pr;
+        // reduce the residual only as far as the outer tolerance still needs (half of the
+        // remaining factor), but never ask FP32 for more than inner_tol
+        const double need = 0.5 * c->opt.tol * bref / std::sqrt(rr);
         CHK(pcg<float>(c, c->rhs32, c->d32, c->r32, c->z32, c->p32, c->q32, true, true, std::sqrt(rr),
-                       c->opt.inner_tol, c->opt.max_iter, -1, true, &pr));
+                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr));
         inner += pr.iters;
         LCHK(c, launch_add_f2d(x, c->d32, n, s));
         sweeps++;
@@ -606,7 +612,7 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     c->opt = *op;
     if (!(c->opt.tol > 0) || c->opt.max_iter <= 0) return fail(c, NM_EINVAL, "tol and max_iter must be positive");
     if (c->opt.precision == NM_PREC_MIXED) {
-        if (!(c->opt.inner_tol > 0)) c->opt.inner_tol = 1e-4;
+        if (!(c->opt.inner_tol > 0)) c->opt.inner_tol = 1e-5;
         if (c->opt.max_sweeps <= 0) c->opt.max_sweeps = 20;
     }
     if (!(c->opt.green_tol > 0)) c->opt.green_tol = c->opt.tol * 1e-2;
@@ -817,6 +823,7 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         local.iters[0] = r1.iters;
         local.iters[1] = r2.iters;
         local.relres = std::sqrt(r1.rr) / std::sqrt(bn);
+        local.relres0 = std::sqrt(r1.rr0) / std::sqrt(bn);
         c->F_last = F;
     } else {
         if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
@@ -830,6 +837,7 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
                             -1, false, &r1));
             local.iters[0] = r1.iters;
             local.relres = std::sqrt(r1.rr) / (bref > 0 ? bref : 1.0);
+            local.relres0 = std::sqrt(r1.rr0) / (bref > 0 ? bref : 1.0);
             if (c->opt.true_residual) {
                 CHK(apply_A<double>(c, c->w, c->q, c->mask));
                 LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));

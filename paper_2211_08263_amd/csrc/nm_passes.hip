@@ -11,11 +11,14 @@
 // unnormalized, inverse ones too; 1/(n1 n2 n3) is folded into the spectral
 // multipliers.
 //
-// Passes of one operator apply q = A p (9 kernels, every pointwise stage
-// fused into a transform pass):
-//   x-fwd(3) | y-fwd(3) | z-fwd, grad, z-inv (3->6) | y-inv(6) |
-//   x-inv, sigma = C:eps, x-fwd (6) | y-fwd(6) | z-fwd, div, z-inv (6->3) |
-//   y-inv(3) | x-inv + rho p (3).
+// Passes of one operator apply q = A p (7 kernels; the derivatives are taken
+// axis by axis, D_x as i xi1 on x spectra, D_y and D_z by single-axis round
+// trips, and every pointwise stage is fused into a transform pass):
+//   x-fwd (3) | y: U -> D_y U (3 -> 6) | z: strain (6 -> 6) |
+//   x-inv, sigma = C : eps, x-fwd (6) | y: D_y and i xi1 terms of div (5 -> 3) |
+//   z: D_z terms, -beta dt^2 scale (6 -> 3) | x-inv + rho p (3).
+// The preconditioner z = M r is x-fwd | y-fwd | z-fwd, (beta dt^2 K + rhobar I)^-1,
+// z-inv | y-inv | x-inv (3 components throughout).
 #include "nm_common.h"
 #include "nm_fft.h"
 #include "nm_passes.h"
@@ -279,12 +282,26 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
     const bool valid = line < (long)lay.n2 * lay.n3;
     const long off = lay.line(line), NS = lay.cs;
     LineAddr<R, (int)sizeof(V)> addr{ll * LP};
+    // issue every global load of the line (six strain spectra and the grain ids) before
+    // the first LDS exchange: the fences of the exchanges would otherwise hold each
+    // component's loads back until the previous component's transform is done
+    V raw[6][R];
+#pragma unroll
+    for (int c = 0; c < 6; c++)
+#pragma unroll
+        for (int m = 0; m < R; m++) raw[c][m] = valid ? spec[c * NS + off + t + m * G] : V{0, 0};
+    uint32_t phw[R];
+    {
+        const uint32_t* ph2 = (const uint32_t*)phase + (valid ? line : 0) * M;
+#pragma unroll
+        for (int m = 0; m < R; m++) phw[m] = ph2[t + m * G];
+    }
     T e[6][2 * R];
 #pragma unroll
     for (int c = 0; c < 6; c++) {
         V v[R];
 #pragma unroll
-        for (int m = 0; m < R; m++) v[m] = valid ? spec[c * NS + off + t + m * G] : V{0, 0};
+        for (int m = 0; m < R; m++) v[m] = raw[c][m];
 #pragma unroll
         for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
         group_sync<true>();
@@ -302,10 +319,9 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
         }
     }
     if (valid) {
-        const uint32_t* ph2 = (const uint32_t*)phase + line * M;
 #pragma unroll
         for (int m = 0; m < R; m++) {
-            const uint32_t ph = ph2[t + m * G];
+            const uint32_t ph = phw[m];
 #pragma unroll
             for (int h = 0; h < 2; h++) {
                 const T* cg = C21 + 21 * (h ? (ph >> 16) : (ph & 0xffffu));
@@ -612,17 +628,36 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
             st(s1, 3 + j, v);
         }
     } else if constexpr (OP == YOP_DIV) {
-        // (source of D_y, source of i xi1, output): sigma Voigt 0..5 = s11 s22 s33 s23 s13 s12
-        constexpr int SRC[3] = {5, 1, 3}, PT[3] = {0, 5, 4};
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
+        // sigma Voigt 0..5 = s11 s22 s33 s23 s13 s12; five components are read once each
+        // (s12 feeds both D_y s12 and i xi1 s12)
+        V s12[R];
+        {
             V v[R], w[R];
-            ld(s2, SRC[j], v);
+            ld(s2, 5, v);
+#pragma unroll
+            for (int m = 0; m < R; m++) s12[m] = v[m];
             deriv(v);
-            ld(s2, PT[j], w);
+            ld(s2, 0, w);
 #pragma unroll
             for (int m = 0; m < R; m++) v[m] = cadd(v[m], ZOps<T>::iscale(w[m], xi1));
-            st(s1, j, v);
+            st(s1, 0, v);
+        }
+        {
+            V v[R];
+            ld(s2, 1, v);
+            deriv(v);
+#pragma unroll
+            for (int m = 0; m < R; m++) v[m] = cadd(v[m], ZOps<T>::iscale(s12[m], xi1));
+            st(s1, 1, v);
+        }
+        {
+            V v[R], w[R];
+            ld(s2, 3, v);
+            deriv(v);
+            ld(s2, 4, w);
+#pragma unroll
+            for (int m = 0; m < R; m++) v[m] = cadd(v[m], ZOps<T>::iscale(w[m], xi1));
+            st(s1, 2, v);
         }
     } else if constexpr (OP == ZOP_STRAIN) {
         const T sc = (T)sp.inv_n1;

@@ -51,11 +51,11 @@ class _Options(C.Structure):
 
 class StepStats(C.Structure):
     _fields_ = [("iters", C.c_int * 2), ("sweeps", C.c_int), ("inner_iters", C.c_int), ("relres", C.c_double),
-                ("t_step_ms", C.c_double), ("t_warm_ms", C.c_double)]
+                ("relres0", C.c_double), ("t_step_ms", C.c_double), ("t_warm_ms", C.c_double)]
 
     def as_dict(self):
         return {"iters": list(self.iters), "sweeps": self.sweeps, "inner_iters": self.inner_iters,
-                "relres": self.relres, "t_step_ms": self.t_step_ms, "t_warm_ms": self.t_warm_ms}
+                "relres": self.relres, "relres0": self.relres0, "t_step_ms": self.t_step_ms, "t_warm_ms": self.t_warm_ms}
 
 
 _lib = None
@@ -111,7 +111,7 @@ class Options:
     route: int = ROUTE_PROJECTED
     tol: float = 1e-8
     max_iter: int = 1000
-    inner_tol: float = 1e-4
+    inner_tol: float = 1e-5
     max_sweeps: int = 20
     warm_start: int = WS_PREV
     green_tol: float = 0.0

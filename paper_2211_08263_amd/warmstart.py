@@ -80,6 +80,22 @@ def target_energy(samples):
     return tot / len(samples)
 
 
+def evaluate(pb, net, steps: int, tol: float = 1e-8):
+    """Mean PCG iterations and mean initial relative residual per step (steps 3..) for
+    each initial iterate on one trajectory."""
+    from . import newmark as nmb
+    res = {}
+    for name, ws in (("cold", nmb.WS_COLD), ("prev", nmb.WS_PREV), ("taylor", nmb.WS_TAYLOR),
+                     ("learned", nmb.WS_LEARNED)):
+        with nmb.newmark_init_problem(pb, nmb.Options(tol=tol, max_iter=500, warm_start=ws)) as ctx:
+            if ws == nmb.WS_LEARNED:
+                nmb.ws_attach(ctx, net)
+            st = [nmb.newmark_step(ctx, pb.U(s + 1)) for s in range(steps)]
+        res[name] = {"iters": float(np.mean([x["iters"][0] for x in st[2:]])),
+                     "relres0": float(np.exp(np.mean([np.log(max(x["relres0"], 1e-300)) for x in st[2:]])))}
+    return res
+
+
 def load_weights(net, path: str = DEFAULT_WEIGHTS) -> bool:
     if not os.path.exists(path):
         return False
@@ -100,7 +116,7 @@ def main():
     args = ap.parse_args()
     import torch
     from . import newmark as nmb
-    from . import workloads as W  # noqa: F401
+    from . import workloads as W
     torch.cuda.set_device(0)
     net = nmb.Net(seed=args.seed)
     t0 = time.time()
@@ -121,12 +137,17 @@ def main():
     t_train = time.time() - t1
     # validation loss: forward only via gradients call (no update)
     vl = float(np.mean([net.gradients(g, f, t)[1] for g, f, t in val]))
+    evals = {}
+    for pb in (W.make_polycrystal(n=64, n_grains=8, seed=1000 + hold, n_steps=args.steps),
+               W.make_polycrystal(n=128, n_grains=62, seed=3000, n_steps=args.steps)):
+        evals[pb.name] = evaluate(pb, net, args.steps)
+        _log(f"[eval] {pb.name}: mean PCG iterations per step {evals[pb.name]}")
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     np.save(args.out, net.get_params().astype(np.float32), allow_pickle=False)
     summary = {"train_samples": len(trn), "val_samples": len(val), "epochs": args.epochs, "lr": args.lr,
                "train_loss_first": hist[0], "train_loss_last": hist[-1], "val_loss": vl,
                "val_zero_correction_loss": e_zero, "val_relative_rms_error": (vl / e_zero) ** 0.5,
-               "train_seconds": t_train, "weights": os.path.relpath(args.out, os.path.dirname(HERE))}
+               "train_seconds": t_train, "mean_iterations": evals, "weights": os.path.relpath(args.out, os.path.dirname(HERE))}
     print(json.dumps(summary), flush=True)
 
 
