@@ -24,6 +24,7 @@ namespace nm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float kLeak = 0.1f;
 constexpr int kFeat = 32;   // padded feature channels
@@ -65,57 +66,168 @@ __device__ __forceinline__ long tap_voxel(int x, int y, int z, int t, const Grid
 // Epilogues: EPI_BF16_ACT  -> BF16 [N][16], leaky ReLU
 //            EPI_F32       -> FP32 [N][ostride] (channels < cout), no activation
 //            EPI_BF16_DACT -> BF16 [N][16] times leaky'(Aprev) (backward data pass)
+//
+// A block owns a 16 (x) by TY (y) column of voxels over ZC consecutive z planes.
+// It keeps three halo planes of the input ((TY + 2) x 18 voxels, all CINP
+// channels, periodic wrap) in LDS and marches along z: while the waves compute
+// one output plane from the three resident planes, the next input plane is
+// already on its way into registers, and it replaces the oldest plane after a
+// barrier.  Every input voxel is read from HBM about (1 + 2/TY)(1 + 2/16)(1 + 2/ZC)
+// times instead of once per tap.  Wave w computes the 16-voxel rows y0 + w + 4 j
+// (four independent MFMA accumulators); the weights stay in registers.
+// LDS plane layout: [kc][row][col][16 channels] BF16, so the 64 lanes of one
+// A-operand read cover 512 contiguous bytes.
 // ---------------------------------------------------------------------------
 enum { EPI_BF16_ACT = 0, EPI_F32 = 1, EPI_BF16_DACT = 2 };
+
+constexpr int kTX = 16;            // x extent of a block tile
+constexpr int kHX = kTX + 2;       // halo columns
+constexpr int kMaxTY = 16;         // y extent of a block tile (rows of 16 voxels)
+constexpr int kHR = kMaxTY + 2;    // halo rows
+
+// Input plane z (wrapped) of a block's halo tile: global -> registers (16-byte chunks,
+// chunk id = (row * 18 + col) * CINP/8 + q) and registers -> one LDS plane slot.
+template <int CINP, int NCH>
+__device__ __forceinline__ void conv_fetch(u32x4 (&buf)[NCH], const uint16_t* __restrict__ X, const Grid& g, int x0,
+                                           int y0, int z, int nchunk)
+{
+    constexpr int QV = CINP / 8;
+    const int zz = z & (g.n3 - 1);
+#pragma unroll
+    for (int k = 0; k < NCH; k++) {
+        // chunks past the tile re-read chunk 0 (always in range) and are not stashed
+        int id = threadIdx.x + 256 * k;
+        id = id < nchunk ? id : 0;
+        const int q = id % QV, vox = id / QV, col = vox % kHX, row = vox / kHX;
+        const int gx = (x0 - 1 + col) & (g.n1 - 1), gy = (y0 - 1 + row) & (g.n2 - 1);
+        buf[k] = *(const u32x4*)(X + (((long)zz * g.n2 + gy) * g.n1 + gx) * CINP + q * 8);
+    }
+}
+template <int CINP, int NCH>
+__device__ __forceinline__ void conv_stash(const u32x4 (&buf)[NCH], uint16_t* dst, int nchunk)
+{
+    constexpr int QV = CINP / 8;
+#pragma unroll
+    for (int k = 0; k < NCH; k++) {
+        const int id = threadIdx.x + 256 * k;
+        if (id < nchunk) {
+            const int q = id % QV, vox = id / QV, col = vox % kHX, row = vox / kHX;
+            *(u32x4*)(dst + (((q >> 1) * kHR + row) * kHX + col) * 16 + (q & 1) * 8) = buf[k];
+        }
+    }
+}
 
 template <int CINP, int EPI>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X, const uint16_t* __restrict__ W,
                                                   const float* __restrict__ bias, void* __restrict__ Y,
                                                   const uint16_t* __restrict__ Aprev, Grid g, int cout, int ostride,
-                                                  long tiles_per_wave)
+                                                  int TY, int ZC)
 {
     constexpr int KC = CINP / 16;
-    const int lane = threadIdx.x & 63;
-    const long wave = (long)blockIdx.x * (blockDim.x / 64) + threadIdx.x / 64;
+    constexpr int QV = CINP / 8;                       // 16-byte chunks per voxel
+    constexpr int PLANE = KC * kHR * kHX * 16;         // BF16 elements per plane slot
+    constexpr int NCH = (kHR * kHX * QV + 255) / 256;  // chunks per thread per plane (upper bound)
+    constexpr int NW = 27 * KC * 64;                   // B-operand fragments (4 BF16 each)
+    __shared__ __align__(16) uint16_t pl[3 * PLANE];
+    __shared__ __align__(16) uint64_t wl[NW];          // [tap][kc][lane] B fragments
+    __shared__ __align__(16) float stg[4][256];
+
+    const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, gq = lane >> 4;
-    bf16x4 wb[27][KC];
-#pragma unroll
-    for (int t = 0; t < 27; t++)
-#pragma unroll
-        for (int kc = 0; kc < KC; kc++) wb[t][kc] = *(const bf16x4*)(W + ((long)(t * 16 + r) * CINP + kc * 16 + 4 * gq));
+    const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
+    const int nrow = TY + 2, nchunk = nrow * kHX * QV;
+
+    // B fragment of lane (co, g) for tap t, chunk kc: W[t][co][kc*16 + 4g .. + 3]
+    for (int e = tid; e < NW; e += 256) {
+        const int l = e % 64, tk = e / 64, kc = tk % KC, t = tk / KC;
+        wl[e] = *(const uint64_t*)(W + ((long)(t * 16 + (l & 15)) * CINP + kc * 16 + 4 * (l >> 4)));
+    }
     const float bcol = (bias && r < cout) ? bias[r] : 0.0f;
-    const long ntiles = g.N / 16;
-    const long t0 = wave * tiles_per_wave;
-    const long t1 = t0 + tiles_per_wave < ntiles ? t0 + tiles_per_wave : ntiles;
-    for (long tile = t0; tile < t1; tile++) {
-        const long v0 = tile * 16;
-        const int x0 = (int)(v0 & (g.n1 - 1));
-        const long yz = v0 / g.n1;
-        const int y = (int)(yz % g.n2), z = (int)(yz / g.n2);
-        f32x4 acc = {0.f, 0.f, 0.f, 0.f};
+
+    u32x4 buf[NCH];
+    conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0 - 1, nchunk);
+    conv_stash<CINP, NCH>(buf, pl, nchunk);
+    conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0, nchunk);
+    conv_stash<CINP, NCH>(buf, pl + PLANE, nchunk);
+    conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0 + 1, nchunk);
+    conv_stash<CINP, NCH>(buf, pl + 2 * PLANE, nchunk);
+    __syncthreads();
+
+    for (int k = 0; k < ZC; k++) {
+        // input plane of the next output, consumed after the barrier
+        if (k + 1 < ZC) conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0 + k + 2, nchunk);
+        f32x4 acc[4];
 #pragma unroll
-        for (int t = 0; t < 27; t++) {
-            const long vox = tap_voxel(x0 + r, y, z, t, g);
+        for (int j = 0; j < 4; j++) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll 1
+        for (int dz = 0; dz < 3; dz++) {
+            const int slot = (k + dz) % 3;
+            const uint16_t* pb = pl + slot * PLANE + r * 16 + 4 * gq;
+            // rows of the four tiles (rows past TY repeat the last one and are not written),
+            // so the MFMA stream below has no branches
+            const uint16_t* pr[4];
 #pragma unroll
-            for (int kc = 0; kc < KC; kc++) {
-                const bf16x4 a = *(const bf16x4*)(X + vox * CINP + kc * 16 + 4 * gq);
-                acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, wb[t][kc], acc, 0, 0, 0);
+            for (int j = 0; j < 4; j++) pr[j] = pb + min(wv + 4 * j, TY - 1) * (kHX * 16);
+            const uint64_t* wbase = wl + dz * 9 * KC * 64 + lane;
+#pragma unroll
+            for (int t9 = 0; t9 < 9; t9++) {
+                const int dy = t9 / 3, dx = t9 % 3; // offsets + 1
+#pragma unroll
+                for (int kc = 0; kc < KC; kc++) {
+                    const uint64_t wfrag = wbase[(t9 * KC + kc) * 64];
+                    bf16x4 b;
+                    memcpy(&b, &wfrag, 8);
+#pragma unroll
+                    for (int j = 0; j < 4; j++) {
+                        const bf16x4 a = *(const bf16x4*)(pr[j] + ((kc * kHR + dy) * kHX + dx) * 16);
+                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
+                    }
+                }
             }
         }
+        const int z = z0 + k;
 #pragma unroll
-        for (int i = 0; i < 4; i++) {
-            const long v = v0 + 4 * gq + i;
-            float o = acc[i] + bcol;
-            if constexpr (EPI == EPI_BF16_ACT) {
-                o = o > 0.f ? o : kLeak * o;
-                ((uint16_t*)Y)[v * kHid + r] = f2bf(o);
-            } else if constexpr (EPI == EPI_BF16_DACT) {
-                const float ap = bf2f(Aprev[v * kHid + r]);
-                o = ap > 0.f ? o : kLeak * o;
-                ((uint16_t*)Y)[v * kHid + r] = f2bf(o);
+        for (int j = 0; j < 4; j++) {
+            const int ty = wv + 4 * j;
+            if (ty >= TY) continue;
+            const long v0 = ((long)z * g.n2 + (y0 + ty)) * g.n1 + x0;
+            if constexpr (EPI == EPI_F32) {
+#pragma unroll
+                for (int i = 0; i < 4; i++)
+                    if (r < cout) ((float*)Y)[(v0 + 4 * gq + i) * ostride + r] = acc[j][i] + bcol;
             } else {
-                if (r < cout) ((float*)Y)[v * ostride + r] = o;
+                // D (voxel 4 gq + i, channel r) -> staging -> lane L owns voxel L / 4, channels 4 (L % 4) .. + 3
+#pragma unroll
+                for (int i = 0; i < 4; i++) stg[wv][(4 * gq + i) * 16 + r] = acc[j][i] + bcol;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                const int vv = lane >> 2, c0 = 4 * (lane & 3);
+                const float4 o4 = *(const float4*)&stg[wv][vv * 16 + c0];
+                float o[4] = {o4.x, o4.y, o4.z, o4.w};
+                if constexpr (EPI == EPI_BF16_ACT) {
+#pragma unroll
+                    for (int c = 0; c < 4; c++) o[c] = o[c] > 0.f ? o[c] : kLeak * o[c];
+                } else {
+                    const uint64_t ap = *(const uint64_t*)(Aprev + (v0 + vv) * kHid + c0);
+#pragma unroll
+                    for (int c = 0; c < 4; c++) {
+                        const float a = bf2f((uint16_t)(ap >> (16 * c)));
+                        o[c] = a > 0.f ? o[c] : kLeak * o[c];
+                    }
+                }
+                const uint64_t w = (uint64_t)f2bf(o[0]) | ((uint64_t)f2bf(o[1]) << 16) |
+                                   ((uint64_t)f2bf(o[2]) << 32) | ((uint64_t)f2bf(o[3]) << 48);
+                *(uint64_t*)((uint16_t*)Y + (v0 + vv) * kHid + c0) = w;
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
+        }
+        if (k + 1 < ZC) {
+            __syncthreads(); // every wave is done with the oldest plane
+            conv_stash<CINP, NCH>(buf, pl + (k % 3) * PLANE, nchunk);
+            __syncthreads();
         }
     }
 }
@@ -355,27 +467,26 @@ __global__ __launch_bounds__(256) void k_target(const double* __restrict__ unext
 static int launch_conv(int cinp, int epi, const uint16_t* X, const uint16_t* W, const float* bias, void* Y,
                        const uint16_t* Aprev, const Grid& g, int cout, int ostride, hipStream_t s)
 {
-    const long ntiles = g.N / 16;
-    long waves = 2048;
-    if (waves > ntiles) waves = ntiles;
-    const long tpw = (ntiles + waves - 1) / waves;
-    waves = (ntiles + tpw - 1) / tpw;
-    const int blocks = (int)((waves + 3) / 4);
+    // tiles: 16 x TY x ZC voxels per block (grid dimensions are powers of two, n1 >= 16)
+    const int TY = g.n2 < kMaxTY ? g.n2 : kMaxTY;
+    const int ZC = g.n3 < 16 ? g.n3 : 16;
+    const dim3 grid(g.n1 / kTX, g.n2 / TY, g.n3 / ZC);
+    if (g.n1 % kTX) return -1;
     if (cinp == 32 && epi == EPI_BF16_ACT)
-        hipLaunchKernelGGL((k_conv_fwd<32, EPI_BF16_ACT>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g,
-                           cout, ostride, tpw);
+        hipLaunchKernelGGL((k_conv_fwd<32, EPI_BF16_ACT>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
+                           ostride, TY, ZC);
     else if (cinp == 32 && epi == EPI_F32)
-        hipLaunchKernelGGL((k_conv_fwd<32, EPI_F32>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
-                           ostride, tpw);
+        hipLaunchKernelGGL((k_conv_fwd<32, EPI_F32>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout, ostride,
+                           TY, ZC);
     else if (cinp == 16 && epi == EPI_BF16_ACT)
-        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_ACT>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g,
-                           cout, ostride, tpw);
+        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_ACT>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
+                           ostride, TY, ZC);
     else if (cinp == 16 && epi == EPI_F32)
-        hipLaunchKernelGGL((k_conv_fwd<16, EPI_F32>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
-                           ostride, tpw);
+        hipLaunchKernelGGL((k_conv_fwd<16, EPI_F32>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout, ostride,
+                           TY, ZC);
     else if (cinp == 16 && epi == EPI_BF16_DACT)
-        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_DACT>), dim3(blocks), dim3(256), 0, s, X, W, bias, Y, Aprev, g,
-                           cout, ostride, tpw);
+        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_DACT>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
+                           ostride, TY, ZC);
     else return -1;
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
