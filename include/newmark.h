@@ -205,6 +205,30 @@ int nm_ws_features(nm_ctx* ctx, void* feat_dev);
  * device FP32 [N][4]. */
 int nm_ws_target(nm_ctx* ctx, void* target_dev);
 
+/* Residual-norm training of the learned start.  The Krylov solve measures the
+ * projected residual, so the network can be trained on it directly: with
+ * x0 = u~_Gamma + s P net(f) (u~_Gamma: the predictor with U(t_{n+1}) on Gamma;
+ * P zeroes Gamma voxels) and r0 = P (b - A x0) = rp - s P A P net(f),
+ *     metric 0:  L = |r0|^2 / cref,            cref  = |r_bar|^2,
+ *     metric 1:  L = r0 . (P M P r0) / crefM,   crefM = r_bar . (P M P r_bar),
+ * rp = P (b - A u~_Gamma), r_bar = P (b - A u_bar) (the reference residual of the
+ * projected solve); A is the operator of eq. (Fourier_ND_A), b that of eq.
+ * (Fourier_ND_b), M the preconditioner of eqs. (precond)-(acous).  Metric 1 weighs
+ * the error roughly in the energy norm that conjugate gradients reduce.
+ * Projected route only.
+ *
+ * Sample (between steps, before the step to t_{n+1}): features (device BF16
+ * [N][32]), rp (device FP64 SoA 3 x N), s, cref and crefM (host; crefM may be
+ * NULL).  U_next as for nm_newmark_step.  The solver state is unchanged. */
+int nm_ws_residual_sample(nm_ctx* ctx, const double* U_next, int per_point, void* feat_dev, void* rp_dev,
+                          double* s_out, double* cref_out, double* crefM_out);
+/* One Adam step (lr) of the attached network on L (metric 0 or 1, with the
+ * matching reference value) for a sample of this context's problem; loss (may
+ * be NULL) receives L before the update.  Synchronous; the solver state is
+ * unchanged. */
+int nm_ws_train_residual(nm_ctx* ctx, const void* feat_dev, const void* rp_dev, double s, double cref, int metric,
+                         float lr, float* loss);
+
 /* The HIP stream (hipStream_t) all of the context's work is queued on. */
 void* nm_get_stream(nm_ctx* ctx);
 

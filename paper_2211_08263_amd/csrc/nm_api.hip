@@ -478,6 +478,26 @@ template <typename T> int precond_impl(nm_ctx* c, const T* r, T* z)
     return chain_precond<T>(c, XF_PLAIN, fa, ia);
 }
 
+// z = P M r (Gamma voxels of the output zeroed), FP64.
+int precond_masked(nm_ctx* c, const double* r, double* z)
+{
+    XFwdArgs fa = xf_args(c, Prec<double>::spec(c));
+    fa.src = r;
+    XInvArgs ia = xi_args(c, Prec<double>::spec(c), z, r, Prec<double>::rho(c), c->mask, nullptr);
+    return chain_precond<double>(c, XF_PLAIN, fa, ia);
+}
+
+// x . y of two 3 x N FP64 fields (deterministic), on the host.
+int dot64(nm_ctx* c, const double* x, const double* y, double* out)
+{
+    const long n = 3 * c->N;
+    LCHK(c, launch_dot<double>(x, y, n, c->part_a, c->stream));
+    LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_SLOT, 6, c->stream));
+    CHK(read_scalars(c));
+    *out = c->hscal[6];
+    return NM_OK;
+}
+
 // Event-timed passes of one operator (which == 0) or preconditioner (which == 1) apply.
 template <typename T> int profile_impl(nm_ctx* c, int which, const T* in, T* out, int reps, double* ms)
 {
@@ -752,21 +772,31 @@ int nm_newmark_init(const nm_problem* pb, const nm_options* op, void* hip_stream
     return st;
 }
 
-static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats* st)
+// Prescribed displacement of the coming step: validated, expanded to 3 components
+// per point (U3) and copied to the device (Ubuf).
+static int upload_U(nm_ctx* c, const double* U_n, int per_point, std::vector<double>& U3)
 {
-    hipStream_t s = c->stream;
-    const long n = 3 * c->N;
     const int d = c->dim;
     const long nU = per_point ? d * c->ng : d;
     if (c->ng > 0 && !U_n) return fail(c, NM_EINVAL, "null prescribed displacement");
-    std::vector<double> U3(per_point ? 3 * c->ng : 3, 0.0);
+    U3.assign(per_point ? 3 * c->ng : 3, 0.0);
     for (long i = 0; c->ng > 0 && i < nU; i++) {
         if (!std::isfinite(U_n[i])) return fail(c, NM_ENAN, "non-finite prescribed displacement");
         if (per_point) U3[3 * (i / d) + i % d] = U_n[i];
         else U3[i] = U_n[i];
     }
     if (c->ng > 0)
-        HIPCHK(c, hipMemcpyAsync(c->Ubuf, U3.data(), U3.size() * sizeof(double), hipMemcpyHostToDevice, s));
+        HIPCHK(c, hipMemcpyAsync(c->Ubuf, U3.data(), U3.size() * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    return NM_OK;
+}
+
+static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats* st)
+{
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    const int d = c->dim;
+    std::vector<double> U3;
+    CHK(upload_U(c, U_n, per_point, U3));
     auto t0 = std::chrono::steady_clock::now();
     // predictor and right-hand side, eq. (Fourier_ND_b)
     LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
@@ -1004,6 +1034,74 @@ int nm_ws_target(nm_ctx* c, void* target_dev)
     if (!c || !c->feat || !target_dev) return fail(c, NM_EINVAL, "call nm_ws_attach first");
     LCHK(c, nm::warm_target(warm_args(c), c->u, (float*)target_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    return NM_OK;
+}
+
+int nm_ws_residual_sample(nm_ctx* c, const double* U_next, int per_point, void* feat_dev, void* rp_dev, double* s_out,
+                          double* cref_out, double* crefM_out)
+{
+    if (!c || !c->feat || !feat_dev || !rp_dev || !s_out || !cref_out)
+        return fail(c, NM_EINVAL, "call nm_ws_attach first and pass every output");
+    if (c->route == NM_ROUTE_GREEN) return fail(c, NM_EINVAL, "residual samples need the projected route");
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    std::vector<double> U3;
+    CHK(upload_U(c, U_next, per_point, U3));
+    // predictor, b = rho u~, features and scale of the coming step
+    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    nm::WarmArgs a = warm_args(c);
+    a.feat = (uint16_t*)feat_dev;
+    LCHK(c, nm::warm_features(a, s));
+    // rp = P (b - A u~_Gamma), u~_Gamma = u~ with U(t_{n+1}) on Gamma
+    double* rp = (double*)rp_dev;
+    LCHK(c, launch_copy<double>(c->w, c->ut, n, s));
+    if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
+    CHK(apply_A<double>(c, c->w, c->q, c->mask));
+    LCHK(c, launch_residual<double>(c->b, c->q, rp, c->mask, c->N, 3, c->part_a, s));
+    double bref;
+    CHK(projected_bref(c, c->w, &bref)); // leaves r_bar = P (b - A u_bar) in c->r
+    if (crefM_out) {
+        CHK(precond_masked(c, c->r, c->z));
+        CHK(dot64(c, c->r, c->z, crefM_out));
+    }
+    HIPCHK(c, hipMemcpyAsync(s_out, c->wscale, sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    *cref_out = bref * bref;
+    return NM_OK;
+}
+
+int nm_ws_train_residual(nm_ctx* c, const void* feat_dev, const void* rp_dev, double scale, double cref, int metric,
+                         float lr, float* loss)
+{
+    if (!c || !c->net || !feat_dev || !rp_dev || !(lr > 0) || !(cref > 0) || !std::isfinite(scale) ||
+        (metric != 0 && metric != 1))
+        return fail(c, NM_EINVAL, "bad arguments (attached network, buffers, metric 0/1, lr > 0, cref > 0)");
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    const uint16_t* feat = (const uint16_t*)feat_dev;
+    nm::WarmArgs a = warm_args(c);
+    // y = s P net(f) ; q = P A y ; r0 = rp - q
+    int e = nm::warm_residual_forward(c->net, a, feat, scale, c->mask, c->p, s);
+    if (e) return fail(c, e == -1 ? NM_EUNSUPPORTED : NM_EHIP, "warm-start network forward failed");
+    CHK(apply_A<double>(c, c->p, c->q, c->mask));
+    LCHK(c, launch_axpby<double>(c->r, (const double*)rp_dev, c->q, -1.0, n, s));
+    double val;
+    const double* wvec = c->r; // the vector the loss gradient pulls back through P A P
+    if (metric == 0) {
+        // L = r0 . r0 / cref
+        CHK(norm2<double>(c, c->r, &val));
+    } else {
+        // L = r0 . (P M P r0) / cref
+        CHK(precond_masked(c, c->r, c->w));
+        CHK(dot64(c, c->r, c->w, &val));
+        wvec = c->w;
+    }
+    // dL/dpred = -2 s P A (r0 or P M P r0) / cref  (A and M symmetric)
+    CHK(apply_A<double>(c, wvec, c->z, c->mask));
+    e = nm::warm_residual_backward(c->net, a, feat, c->z, -2.0 * scale / cref, lr, s);
+    if (e) return fail(c, NM_EHIP, "warm-start network backward failed");
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (loss) *loss = (float)(val / cref);
     return NM_OK;
 }
 

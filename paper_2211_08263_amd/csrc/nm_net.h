@@ -31,5 +31,11 @@ struct WarmArgs {
 int warm_features(const WarmArgs& a, hipStream_t s);
 int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s);
 int warm_target(const WarmArgs& a, const double* unext, float* target, hipStream_t s);
+// Residual-norm training: y = scale * P net(feat) (FP64 SoA, Gamma voxels zero) ...
+int warm_residual_forward(nm_net* net, const WarmArgs& a, const uint16_t* feat, double scale, const uint8_t* mask,
+                          double* y, hipStream_t s);
+// ... then, with dL/dpred = scale * gsoa (FP64 SoA), backward pass and one Adam step.
+int warm_residual_backward(nm_net* net, const WarmArgs& a, const uint16_t* feat, const double* gsoa, double scale,
+                           float lr, hipStream_t s);
 
 } // namespace nm

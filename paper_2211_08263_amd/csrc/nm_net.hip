@@ -461,6 +461,36 @@ __global__ __launch_bounds__(256) void k_target(const double* __restrict__ unext
     }
 }
 
+// y = s * P pred as FP64 SoA 3 x N (Gamma voxels zero)
+__global__ __launch_bounds__(256) void k_pred_soa(const float* __restrict__ pred, double s,
+                                                  const uint8_t* __restrict__ mask, long N, double* __restrict__ y)
+{
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
+        const bool fixed = mask && mask[v];
+#pragma unroll
+        for (int c = 0; c < 3; c++) y[c * N + v] = fixed ? 0.0 : s * (double)pred[v * kPredStride + c];
+    }
+}
+
+// dz (BF16 [N][16]) = scale * g (FP64 SoA 3 x N), channels >= 3 zero
+__global__ __launch_bounds__(256) void k_dz_soa(const double* __restrict__ g, double scale, long N,
+                                                uint16_t* __restrict__ dz)
+{
+    for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
+        uint16_t o[kHid];
+#pragma unroll
+        for (int c = 0; c < kHid; c++) o[c] = 0;
+#pragma unroll
+        for (int c = 0; c < kOutC; c++) o[c] = f2bf((float)(scale * g[c * N + v]));
+#pragma unroll
+        for (int c = 0; c < kHid; c += 4) {
+            const uint64_t w = (uint64_t)o[c] | ((uint64_t)o[c + 1] << 16) | ((uint64_t)o[c + 2] << 32) |
+                               ((uint64_t)o[c + 3] << 48);
+            *(uint64_t*)(dz + v * kHid + c) = w;
+        }
+    }
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -682,6 +712,37 @@ static int net_forward(nm_net* n, const Grid& g, const uint16_t* feat, hipStream
     return NM_OK;
 }
 
+// Backward pass from dL/dpred already in dz0 (BF16 [N][16], channels >= 3 zero):
+// parameter gradients into gr.  Needs the activations of a forward pass on feat.
+static int net_backward(nm_net* n, const Grid& g, const uint16_t* feat, hipStream_t s)
+{
+    uint16_t *dz = n->dz0, *dznext = n->dz1;
+    for (int l = n->L - 1; l >= 0; l--) {
+        const uint16_t* in = l == 0 ? feat : n->act[l];
+        float* gW = n->gr + n->off[l];
+        if (launch_bwdw(n->cinp[l], in, dz, n->partial, gW, gW + layer_w(n, l), n->cin[l], n->cout[l], g, s))
+            return NM_EHIP;
+        if (l > 0) {
+            // dZ_{l-1} = (W_l^T * dZ_l) . leaky'(A_{l-1}),  A_{l-1} = act[l]
+            if (launch_conv(16, EPI_BF16_DACT, dz, n->wb[l], nullptr, dznext, n->act[l], g, 16, 16, s))
+                return NM_EHIP;
+            std::swap(dz, dznext);
+        }
+    }
+    return NM_OK;
+}
+
+// Adam step on the master parameters and BF16 repack.
+static int net_adam(nm_net* n, float lr, hipStream_t s)
+{
+    n->step++;
+    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
+    const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
+    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->nparam + 255) / 256)), dim3(256), 0, s, n->p, n->gr, n->m, n->v,
+                       n->nparam, lr, b1, b2, eps, c1, c2);
+    return net_pack(n, s);
+}
+
 int nm_net_forward(nm_net* n, void* stream, const int* grid, const void* feat_dev, void* pred_dev)
 {
     if (!n || !grid || !feat_dev || !pred_dev) return NM_EINVAL;
@@ -706,27 +767,8 @@ int nm_net_train_step(nm_net* n, void* stream, const int* grid, const void* feat
     // loss and dL/dpred
     const int lb = 512;
     hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, n->pred, (const float*)target_dev, n->dz0, g.N, n->red);
-    // backward through the layers: dz0 holds dL/dZ_l
-    uint16_t *dz = n->dz0, *dznext = n->dz1;
-    for (int l = n->L - 1; l >= 0; l--) {
-        const uint16_t* in = l == 0 ? feat : n->act[l];
-        float* gW = n->gr + n->off[l];
-        float* gb = gW + layer_w(n, l);
-        if (launch_bwdw(n->cinp[l], in, dz, n->partial, gW, gb, n->cin[l], n->cout[l], g, s)) return NM_EHIP;
-        if (l > 0) {
-            // dZ_{l-1} = (W_l^T * dZ_l) . leaky'(A_{l-1}),  A_{l-1} = act[l]
-            if (launch_conv(16, EPI_BF16_DACT, dz, n->wb[l], nullptr, dznext, n->act[l], g, 16, 16, s))
-                return NM_EHIP;
-            std::swap(dz, dznext);
-        }
-    }
-    // Adam step and BF16 repack
-    n->step++;
-    const float b1 = 0.9f, b2 = 0.999f, eps = 1e-8f;
-    const float c1 = 1.f - std::pow(b1, (float)n->step), c2 = 1.f - std::pow(b2, (float)n->step);
-    hipLaunchKernelGGL(k_adam, dim3((unsigned)((n->nparam + 255) / 256)), dim3(256), 0, s, n->p, n->gr, n->m, n->v,
-                       n->nparam, lr, b1, b2, eps, c1, c2);
-    if (net_pack(n, s) != NM_OK) return NM_EHIP;
+    CHECK_NM(net_backward(n, g, feat, s));
+    if (net_adam(n, lr, s) != NM_OK) return NM_EHIP;
     if (loss) {
         std::vector<double> part(lb);
         if (hipMemcpyAsync(part.data(), n->red, lb * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess)
@@ -753,18 +795,7 @@ int nm_net_gradients(nm_net* n, void* stream, const int* grid, const void* feat_
     CHECK_NM(net_forward(n, g, feat, s));
     const int lb = 512;
     hipLaunchKernelGGL(k_loss, dim3(lb), dim3(256), 0, s, n->pred, (const float*)target_dev, n->dz0, g.N, n->red);
-    uint16_t *dz = n->dz0, *dznext = n->dz1;
-    for (int l = n->L - 1; l >= 0; l--) {
-        const uint16_t* in = l == 0 ? feat : n->act[l];
-        float* gW = n->gr + n->off[l];
-        if (launch_bwdw(n->cinp[l], in, dz, n->partial, gW, gW + layer_w(n, l), n->cin[l], n->cout[l], g, s))
-            return NM_EHIP;
-        if (l > 0) {
-            if (launch_conv(16, EPI_BF16_DACT, dz, n->wb[l], nullptr, dznext, n->act[l], g, 16, 16, s))
-                return NM_EHIP;
-            std::swap(dz, dznext);
-        }
-    }
+    CHECK_NM(net_backward(n, g, feat, s));
     std::vector<double> part(lb);
     if (hipMemcpyAsync(part.data(), n->red, lb * sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
         hipMemcpyAsync(grad_host, n->gr, n->nparam * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
@@ -867,6 +898,27 @@ int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
 int warm_target(const WarmArgs& a, const double* unext, float* target, hipStream_t s)
 {
     hipLaunchKernelGGL(k_target, dim3(2048), dim3(256), 0, s, unext, a.ut, a.scale, target, a.N);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int warm_residual_forward(nm_net* net, const WarmArgs& a, const uint16_t* feat, double scale, const uint8_t* mask,
+                          double* y, hipStream_t s)
+{
+    Grid g{a.n1, a.n2, a.n3, a.N};
+    int n3[3] = {a.n1, a.n2, a.n3};
+    if (check_grid(n3) != NM_OK) return -1;
+    if (net_forward(net, g, feat, s) != NM_OK) return -2;
+    hipLaunchKernelGGL(k_pred_soa, dim3(2048), dim3(256), 0, s, net->pred, scale, mask, a.N, y);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int warm_residual_backward(nm_net* net, const WarmArgs& a, const uint16_t* feat, const double* gsoa, double scale,
+                           float lr, hipStream_t s)
+{
+    Grid g{a.n1, a.n2, a.n3, a.N};
+    hipLaunchKernelGGL(k_dz_soa, dim3(2048), dim3(256), 0, s, gsoa, scale, a.N, net->dz0);
+    if (net_backward(net, g, feat, s) != NM_OK) return -2;
+    if (net_adam(net, lr, s) != NM_OK) return -2;
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -26,7 +26,7 @@ EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_preco
             "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream", "nm_profile_passes",
             "nm_net_create", "nm_net_destroy", "nm_net_num_params", "nm_net_get_params", "nm_net_set_params",
             "nm_net_forward", "nm_net_train_step", "nm_net_gradients", "nm_conv3d_bf16", "nm_ws_attach",
-            "nm_ws_features", "nm_ws_target",
+            "nm_ws_features", "nm_ws_target", "nm_ws_residual_sample", "nm_ws_train_residual",
             "nm_last_error", "nm_destroy")
 
 
@@ -95,6 +95,10 @@ def load_library():
     L.nm_ws_attach.argtypes = [vp, vp]
     L.nm_ws_features.argtypes = [vp, vp]
     L.nm_ws_target.argtypes = [vp, vp]
+    L.nm_ws_residual_sample.argtypes = [vp, vp, C.c_int, vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
+                                        C.POINTER(C.c_double)]
+    L.nm_ws_train_residual.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_int, C.c_float,
+                                       C.POINTER(C.c_float)]
     L.nm_get_stream.argtypes = [vp]
     L.nm_get_stream.restype = vp
     L.nm_last_error.argtypes = [vp]
@@ -400,3 +404,20 @@ def ws_features(ctx: Context, feat=None) -> None:
 
 def ws_target(ctx: Context, target) -> None:
     ctx.check(load_library().nm_ws_target(ctx.handle, target.data_ptr()))
+
+
+def ws_residual_sample(ctx: Context, U_next, feat, rp, per_point: bool = False):
+    """Features and projected residual of the predictor for the coming step; returns
+    (s, cref, crefM)."""
+    U = _c64(U_next).reshape(-1)
+    sv, cv, cm = C.c_double(), C.c_double(), C.c_double()
+    ctx.check(load_library().nm_ws_residual_sample(ctx.handle, U.ctypes.data, int(bool(per_point)), feat.data_ptr(),
+                                                   rp.data_ptr(), C.byref(sv), C.byref(cv), C.byref(cm)))
+    return sv.value, cv.value, cm.value
+
+
+def ws_train_residual(ctx: Context, feat, rp, s: float, cref: float, lr: float, metric: int = 0) -> float:
+    loss = C.c_float()
+    ctx.check(load_library().nm_ws_train_residual(ctx.handle, feat.data_ptr(), rp.data_ptr(), float(s), float(cref),
+                                                  int(metric), float(lr), C.byref(loss)))
+    return loss.value

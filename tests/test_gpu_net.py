@@ -248,3 +248,102 @@ def test_features_and_target_match_the_newmark_state():
     errt = np.abs(tg[:, :3] - wt).max() / np.abs(wt).max()
     print(f"target: max err {errt:.2e}", flush=True)
     assert errt < 1e-6 and tg[:, 3].max() == 0 and tg[:, 3].min() == 0
+
+
+def test_residual_sample_and_loss_match_the_oracle_operator():
+    """rp = P(b - A u~_Gamma), cref = |P(b - A u_bar)|^2 and the residual-norm loss of the
+    learned start, recomputed with the oracle's FP64 operator; the solver state is untouched."""
+    import torch
+    pb = W.make_polycrystal(n=16, n_grains=4, seed=1004, n_steps=8)
+    N = pb.n_vox
+    op = oracle.OracleProblem.from_problem(pb)
+    fixed = np.zeros(N, bool)
+    fixed[pb.gamma_idx] = True
+    net = nmb.Net(seed=3)
+    with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10, max_iter=500)) as ctx:
+        nmb.ws_attach(ctx, net)
+        for s in range(4):
+            nmb.newmark_step(ctx, pb.U(s + 1))
+        st = nmb.get_state(ctx)
+        f = torch.empty(N * 32, dtype=torch.int16, device="cuda")
+        rp = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+        sc, cref, crefm = nmb.ws_residual_sample(ctx, pb.U(5), f, rp)
+        pred = torch.empty(N * 4, dtype=torch.float32, device="cuda")
+        net.forward(pb.n, f, pred)
+        loss = nmb.ws_train_residual(ctx, f, rp, sc, cref, lr=1e-3, metric=0)
+        pred2 = torch.empty_like(pred)
+        net.forward(pb.n, f, pred2)
+        lossm = nmb.ws_train_residual(ctx, f, rp, sc, crefm, lr=1e-3, metric=1)
+        st2 = nmb.get_state(ctx)
+    net.close()
+    for k in ("u", "v", "a"):
+        assert np.array_equal(st[k], st2[k])
+
+    def A(x):
+        return op.apply(x.reshape(op.field_shape)).reshape(3, N)
+
+    def PM(x):
+        z = op.precond(x.reshape(op.field_shape)).reshape(3, N)
+        z[:, fixed] = 0
+        return z
+
+    u, v, a = (st[k].reshape(3, N) for k in ("u", "v", "a"))
+    ut = u + pb.dt * v + pb.dt ** 2 * (0.5 - pb.beta) * a
+    U5 = pb.U(5)[:, None]
+    b = pb.rho[pb.phase_id.reshape(-1)][None, :] * ut
+    utg = ut.copy()
+    utg[:, fixed] = U5
+    rp_want = b - A(utg)
+    rp_want[:, fixed] = 0
+    ubar = np.zeros((3, N))
+    ubar[:, fixed] = U5
+    r_bar = b - A(ubar)
+    r_bar[:, fixed] = 0
+    cref_want = float((r_bar ** 2).sum())
+    s_want = float(np.sqrt(np.mean((ut - u) ** 2)))
+    got = rp.cpu().numpy().reshape(3, N)
+    e_rp = np.abs(got - rp_want).max() / np.abs(rp_want).max()
+    print(f"rp err {e_rp:.2e}, cref {cref:.6e} vs {cref_want:.6e}, s {sc:.6e} vs {s_want:.6e}", flush=True)
+    assert e_rp < 1e-12
+    assert abs(cref - cref_want) <= 1e-12 * cref_want
+    assert abs(sc - s_want) <= 1e-12 * s_want
+    y = sc * pred.cpu().numpy().astype(np.float64).reshape(N, 4)[:, :3].T
+    y[:, fixed] = 0
+    r0 = rp_want - A(y)
+    r0[:, fixed] = 0
+    loss_want = float((r0 ** 2).sum()) / cref_want
+    print(f"loss {loss:.7g} vs {loss_want:.7g}", flush=True)
+    assert abs(loss - loss_want) <= 1e-5 * loss_want
+    crefm_want = float((r_bar * PM(r_bar)).sum())
+    assert abs(crefm - crefm_want) <= 1e-12 * crefm_want
+    y2 = sc * pred2.cpu().numpy().astype(np.float64).reshape(N, 4)[:, :3].T
+    y2[:, fixed] = 0
+    r02 = rp_want - A(y2)
+    r02[:, fixed] = 0
+    lossm_want = float((r02 * PM(r02)).sum()) / crefm_want
+    print(f"energy loss {lossm:.7g} vs {lossm_want:.7g}", flush=True)
+    assert abs(lossm - lossm_want) <= 1e-5 * lossm_want
+
+
+def test_residual_training_lowers_the_initial_residual():
+    import torch
+    pb = W.make_polycrystal(n=32, n_grains=8, seed=1005, n_steps=14)
+    N = pb.n_vox
+    net = nmb.Net(seed=4)
+    with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10, max_iter=500, warm_start=nmb.WS_COLD)) as ctx:
+        nmb.ws_attach(ctx, net)
+        samples = []
+        for s in range(14):
+            f = torch.empty(N * 32, dtype=torch.int16, device="cuda")
+            rp = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+            sc, cref, crefm = nmb.ws_residual_sample(ctx, pb.U(s + 1), f, rp)
+            nmb.newmark_step(ctx, pb.U(s + 1))
+            if s >= 4:
+                samples.append((f, rp, sc, crefm))
+        losses = []
+        for epoch in range(30):
+            losses.append(np.mean([nmb.ws_train_residual(ctx, f, rp, sc, crefm, lr=2e-3, metric=1)
+                                   for f, rp, sc, crefm in samples]))
+    print("residual training losses", [f"{x:.4g}" for x in losses[::5]], losses[-1], flush=True)
+    assert losses[-1] < 0.5 * losses[0]
+    net.close()
