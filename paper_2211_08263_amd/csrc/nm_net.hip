@@ -23,6 +23,7 @@
 namespace nm {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -117,6 +118,16 @@ __device__ __forceinline__ void conv_stash(const u32x4 (&buf)[NCH], uint16_t* ds
     }
 }
 
+// K steps of one output plane: CINP == 32 takes one tap (32 channels) per
+// 16x16x32 MFMA; CINP == 16 takes two taps (16 channels each) per MFMA, lanes
+// 0-31 of the A/B operands holding tap 2s and lanes 32-63 tap 2s + 1 (the 28th
+// tap is padding with zero weights).
+template <int CINP> struct ConvK {
+    static constexpr int STEPS = CINP == 32 ? 27 : 14;
+    // tap whose channels lane group gq (0..3) supplies at step s
+    static __device__ __forceinline__ int tap(int s, int gq) { return CINP == 32 ? s : 2 * s + (gq >> 1); }
+};
+
 template <int CINP, int EPI>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X, const uint16_t* __restrict__ W,
                                                   const float* __restrict__ bias, void* __restrict__ Y,
@@ -124,65 +135,73 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
                                                   int TY, int ZC)
 {
     constexpr int KC = CINP / 16;
-    constexpr int QV = CINP / 8;                       // 16-byte chunks per voxel
     constexpr int PLANE = KC * kHR * kHX * 16;         // BF16 elements per plane slot
-    constexpr int NCH = (kHR * kHX * QV + 255) / 256;  // chunks per thread per plane (upper bound)
-    constexpr int NW = 27 * KC * 64;                   // B-operand fragments (4 BF16 each)
+    constexpr int NCH = (kHR * kHX * (CINP / 8) + 255) / 256;
+    constexpr int STEPS = ConvK<CINP>::STEPS;
     __shared__ __align__(16) uint16_t pl[3 * PLANE];
-    __shared__ __align__(16) uint64_t wl[NW];          // [tap][kc][lane] B fragments
+    __shared__ __align__(16) bf16x8 wl[STEPS * 64];    // [step][lane] B fragments
     __shared__ __align__(16) float stg[4][256];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
     const int r = lane & 15, gq = lane >> 4;
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
-    const int nrow = TY + 2, nchunk = nrow * kHX * QV;
+    const int nchunk = (TY + 2) * kHX * (CINP / 8);
 
-    // B fragment of lane (co, g) for tap t, chunk kc: W[t][co][kc*16 + 4g .. + 3]
-    for (int e = tid; e < NW; e += 256) {
-        const int l = e % 64, tk = e / 64, kc = tk % KC, t = tk / KC;
-        wl[e] = *(const uint64_t*)(W + ((long)(t * 16 + (l & 15)) * CINP + kc * 16 + 4 * (l >> 4)));
+    // B fragment of lane (co, gq) at step s: W[tap][co][ci .. ci + 7] (zero past the last tap)
+    for (int e = tid; e < STEPS * 64; e += 256) {
+        const int l = e % 64, st = e / 64, lg = l >> 4;
+        const int t = ConvK<CINP>::tap(st, lg);
+        const int ci = CINP == 32 ? 8 * lg : 8 * (lg & 1);
+        bf16x8 w = {0, 0, 0, 0, 0, 0, 0, 0};
+        if (t < 27) w = *(const bf16x8*)(W + ((long)(t * 16 + (l & 15)) * CINP + ci));
+        wl[e] = w;
     }
     const float bcol = (bias && r < cout) ? bias[r] : 0.0f;
 
-    u32x4 buf[NCH];
-    conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0 - 1, nchunk);
-    conv_stash<CINP, NCH>(buf, pl, nchunk);
-    conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0, nchunk);
-    conv_stash<CINP, NCH>(buf, pl + PLANE, nchunk);
-    conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0 + 1, nchunk);
-    conv_stash<CINP, NCH>(buf, pl + 2 * PLANE, nchunk);
+    // A operand of this lane at step s: its tap's (dz, dy, dx) and channel offset
+    int aoff[STEPS], adz[STEPS];
+#pragma unroll
+    for (int st = 0; st < STEPS; st++) {
+        int t = ConvK<CINP>::tap(st, gq);
+        t = t < 27 ? t : 26; // padding tap: any finite input, zero weights
+        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        const int kc = CINP == 32 ? (gq >> 1) : 0;
+        adz[st] = dz;
+        aoff[st] = ((kc * kHR + dy) * kHX + dx + r) * 16 + 8 * (gq & 1);
+    }
+
+    u32x4 bufA[NCH], bufB[NCH];
+    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0 - 1, nchunk);
+    conv_stash<CINP, NCH>(bufA, pl, nchunk);
+    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0, nchunk);
+    conv_stash<CINP, NCH>(bufA, pl + PLANE, nchunk);
+    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0 + 1, nchunk);
+    conv_stash<CINP, NCH>(bufA, pl + 2 * PLANE, nchunk);
+    if (ZC > 1) conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0 + 2, nchunk);
     __syncthreads();
 
-    for (int k = 0; k < ZC; k++) {
-        // input plane of the next output, consumed after the barrier
-        if (k + 1 < ZC) conv_fetch<CINP, NCH>(buf, X, g, x0, y0, z0 + k + 2, nchunk);
+    // Output plane k: the plane two ahead (z0 + k + 3) is fetched into one register set
+    // while the plane one ahead (z0 + k + 2, fetched a plane earlier) waits in the other
+    // and replaces the oldest LDS plane after the compute.
+    auto plane = [&](int k, u32x4 (&cur)[NCH], u32x4 (&nxt)[NCH]) {
+        if (k + 2 < ZC) conv_fetch<CINP, NCH>(nxt, X, g, x0, y0, z0 + k + 3, nchunk);
+        const uint16_t* sb[3];
+#pragma unroll
+        for (int dz = 0; dz < 3; dz++) sb[dz] = pl + ((k + dz) % 3) * PLANE;
+        int rowoff[4];
+#pragma unroll
+        for (int j = 0; j < 4; j++) rowoff[j] = min(wv + 4 * j, TY - 1) * (kHX * 16); // rows past TY: not written
         f32x4 acc[4];
 #pragma unroll
         for (int j = 0; j < 4; j++) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll 1
-        for (int dz = 0; dz < 3; dz++) {
-            const int slot = (k + dz) % 3;
-            const uint16_t* pb = pl + slot * PLANE + r * 16 + 4 * gq;
-            // rows of the four tiles (rows past TY repeat the last one and are not written),
-            // so the MFMA stream below has no branches
-            const uint16_t* pr[4];
 #pragma unroll
-            for (int j = 0; j < 4; j++) pr[j] = pb + min(wv + 4 * j, TY - 1) * (kHX * 16);
-            const uint64_t* wbase = wl + dz * 9 * KC * 64 + lane;
+        for (int st = 0; st < STEPS; st++) {
+            const bf16x8 b = wl[st * 64 + lane];
+            const uint16_t* a0 = (adz[st] == 0 ? sb[0] : adz[st] == 1 ? sb[1] : sb[2]) + aoff[st];
 #pragma unroll
-            for (int t9 = 0; t9 < 9; t9++) {
-                const int dy = t9 / 3, dx = t9 % 3; // offsets + 1
-#pragma unroll
-                for (int kc = 0; kc < KC; kc++) {
-                    const uint64_t wfrag = wbase[(t9 * KC + kc) * 64];
-                    bf16x4 b;
-                    memcpy(&b, &wfrag, 8);
-#pragma unroll
-                    for (int j = 0; j < 4; j++) {
-                        const bf16x4 a = *(const bf16x4*)(pr[j] + ((kc * kHR + dy) * kHX + dx) * 16);
-                        acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[j], 0, 0, 0);
-                    }
-                }
+            for (int j = 0; j < 4; j++) {
+                const bf16x8 a = *(const bf16x8*)(a0 + rowoff[j]);
+                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
             }
         }
         const int z = z0 + k;
@@ -212,8 +231,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
                     const uint64_t ap = *(const uint64_t*)(Aprev + (v0 + vv) * kHid + c0);
 #pragma unroll
                     for (int c = 0; c < 4; c++) {
-                        const float a = bf2f((uint16_t)(ap >> (16 * c)));
-                        o[c] = a > 0.f ? o[c] : kLeak * o[c];
+                        const float av = bf2f((uint16_t)(ap >> (16 * c)));
+                        o[c] = av > 0.f ? o[c] : kLeak * o[c];
                     }
                 }
                 const uint64_t w = (uint64_t)f2bf(o[0]) | ((uint64_t)f2bf(o[1]) << 16) |
@@ -226,9 +245,13 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
         }
         if (k + 1 < ZC) {
             __syncthreads(); // every wave is done with the oldest plane
-            conv_stash<CINP, NCH>(buf, pl + (k % 3) * PLANE, nchunk);
+            conv_stash<CINP, NCH>(cur, pl + (k % 3) * PLANE, nchunk);
             __syncthreads();
         }
+    };
+    for (int k = 0; k < ZC; k += 2) {
+        plane(k, bufA, bufB);
+        if (k + 1 < ZC) plane(k + 1, bufB, bufA);
     }
 }
 
