@@ -794,6 +794,9 @@ int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* ph
 #ifndef NM_ZSPEC_R64
 #define NM_ZSPEC_R64 8
 #endif
+#ifndef NM_ZSPEC_R32
+#define NM_ZSPEC_R32 8
+#endif
 #ifndef NM_ZSPEC_BLK64
 #define NM_ZSPEC_BLK64 256
 #endif
@@ -801,7 +804,7 @@ int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* ph
 template <int L> constexpr int ypass_radix() { return L >= 16 ? 16 : L; }
 template <typename T, int L> constexpr int zspec_radix()
 {
-    return L < 8 ? L : (sizeof(T) == 8 ? (NM_ZSPEC_R64 < L ? NM_ZSPEC_R64 : L) : (L >= 16 ? 16 : L));
+    return L < 8 ? L : (sizeof(T) == 8 ? (NM_ZSPEC_R64 < L ? NM_ZSPEC_R64 : L) : (NM_ZSPEC_R32 < L ? NM_ZSPEC_R32 : L));
 }
 template <typename T> constexpr int zspec_block() { return sizeof(T) == 8 ? NM_ZSPEC_BLK64 : 256; }
 
