@@ -68,6 +68,7 @@ struct nm_ctx {
     float2* spec32b = nullptr;
     // Gamma buffers
     double* Ubuf = nullptr; // dim * max(ng, 1)
+    double* lift = nullptr; // projected route: A e_c, e_c = unit component c on Gamma (3 x (3 x N))
     double* gbuf = nullptr; // dim * max(ng, 1)
     std::vector<double> G, LU, F_last;
     std::vector<int> piv;
@@ -242,21 +243,25 @@ struct PcgResult {
 
 // Preconditioned conjugate gradients (Hestenes-Stiefel) on real-space vectors.
 // x: initial guess / solution.  With masked, P A P and P M P on the free dofs.
+// rr_known >= 0: r already holds P (rhs - A x) with r.r = rr_known (no initial apply).
 template <typename T>
 int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool x_zero, double bref, double tol,
-        int max_iter, int fixed_iters, bool allow_unconverged, PcgResult* res)
+        int max_iter, int fixed_iters, bool allow_unconverged, PcgResult* res, double rr_known = -1.0)
 {
     hipStream_t s = c->stream;
     const uint8_t* mk = masked ? c->mask : nullptr;
     const long n = 3 * c->N;
     void* spec = Prec<T>::spec(c);
     // r = P (b - A x)
-    if (x_zero) LCHK(c, launch_fill<T>(q, (T)0, n, s));
-    else CHK(apply_A<T>(c, x, q, mk));
-    LCHK(c, launch_residual<T>(rhs, q, r, mk, c->N, 3, c->part_a, s));
-    LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
-    CHK(read_scalars(c));
-    double rr = c->hscal[S_RR];
+    double rr = rr_known;
+    if (rr_known < 0) {
+        if (x_zero) LCHK(c, launch_fill<T>(q, (T)0, n, s));
+        else CHK(apply_A<T>(c, x, q, mk));
+        LCHK(c, launch_residual<T>(rhs, q, r, mk, c->N, 3, c->part_a, s));
+        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+        CHK(read_scalars(c));
+        rr = c->hscal[S_RR];
+    }
     res->iters = 0;
     res->rr = rr;
     res->rr0 = rr;
@@ -339,8 +344,21 @@ int projected_bref(nm_ctx* c, const double* x, double* bref)
     return NM_OK;
 }
 
+// The same for a uniform prescribed displacement U3 from the precomputed lifting
+// responses (no operator apply); r_bar = P (b - A u_bar) is left in c->r.
+int lift_bref(nm_ctx* c, const double* U3, double* bref)
+{
+    hipStream_t s = c->stream;
+    LCHK(c, launch_lift_residual(c->b, c->lift, U3, c->mask, c->N, c->r, c->part_a, s));
+    LCHK(c, launch_reduce(c->part_a, vec_blocks(3 * c->N), c->scal, RED_STORE_RR, 0, s));
+    CHK(read_scalars(c));
+    *bref = std::sqrt(c->hscal[S_RR]);
+    return NM_OK;
+}
+
 // Mixed precision: FP64 residual r = P(b - A x), FP32 PCG correction, x += d.
-int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st)
+// rr_known >= 0: c->r already holds the first sweep's residual P (b - A x), r.r = rr_known.
+int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_known = -1.0)
 {
     hipStream_t s = c->stream;
     const long n = 3 * c->N;
@@ -348,11 +366,15 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st)
     int sweeps = 0, inner = 0;
     double rr = 0;
     for (;;) {
-        CHK(apply_A<double>(c, x, c->q, c->mask));
-        LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
-        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
-        CHK(read_scalars(c));
-        rr = c->hscal[S_RR];
+        if (sweeps == 0 && rr_known >= 0) {
+            rr = rr_known;
+        } else {
+            CHK(apply_A<double>(c, x, c->q, c->mask));
+            LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+            LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+            CHK(read_scalars(c));
+            rr = c->hscal[S_RR];
+        }
         if (sweeps == 0 && st) st->relres0 = std::sqrt(rr) / bref;
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual in refinement sweep %d", sweeps);
         if (std::sqrt(rr) <= c->opt.tol * bref) break;
@@ -587,6 +609,25 @@ void nm_destroy(nm_ctx* c)
     delete c;
 }
 
+// Lifting responses of the projected route: lift_c = A e_c with e_c the unit
+// displacement in component c on every Gamma voxel (zero elsewhere), so that
+// A u_bar = sum_c U_c lift_c for a displacement U uniform on Gamma.
+static int build_lift(nm_ctx* c)
+{
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    CHK(dalloc(c, &c->lift, 3 * n));
+    for (int comp = 0; comp < 3; comp++) {
+        const double e[3] = {comp == 0 ? 1.0 : 0.0, comp == 1 ? 1.0 : 0.0, comp == 2 ? 1.0 : 0.0};
+        HIPCHK(c, hipMemcpyAsync(c->Ubuf, e, sizeof(e), hipMemcpyHostToDevice, s));
+        LCHK(c, launch_fill<double>(c->z, 0.0, n, s));
+        LCHK(c, launch_set_gamma(c->z, c->gidx, c->ng, c->Ubuf, 0, 3, c->N, s));
+        CHK(apply_A<double>(c, c->z, c->lift + comp * n, nullptr));
+        HIPCHK(c, hipStreamSynchronize(s)); // e is a stack buffer and Ubuf is reused
+    }
+    return NM_OK;
+}
+
 static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
 {
     if (!pb || !op) return fail(c, NM_EINVAL, "null problem or options");
@@ -757,6 +798,7 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
         LCHK(c, launch_accel0(c->a, c->u, c->q, c->phase, c->rho64, c->N, 3, c->sp.bdt2, s));
     }
     if (c->route == NM_ROUTE_GREEN && c->ng > 0) CHK(build_green(c));
+    if (c->route == NM_ROUTE_PROJECTED && c->ng > 0) CHK(build_lift(c));
     HIPCHK(c, hipStreamSynchronize(s));
     return NM_OK;
 }
@@ -857,14 +899,19 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         c->F_last = F;
     } else {
         if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
+        // reference residual r_bar = P (b - A u_bar) (left in c->r); from the lifting
+        // responses when U is uniform on Gamma
         double bref;
-        CHK(projected_bref(c, c->w, &bref));
+        if (c->lift && !per_point) CHK(lift_bref(c, U3.data(), &bref));
+        else CHK(projected_bref(c, c->w, &bref));
+        // the zero start is u_bar itself, so its initial residual is r_bar
+        const double rr0 = c->opt.warm_start == NM_WS_COLD ? bref * bref : -1.0;
         if (c->opt.precision == NM_PREC_MIXED) {
-            CHK(solve_mixed(c, c->w, bref, &local));
+            CHK(solve_mixed(c, c->w, bref, &local, rr0));
         } else {
             PcgResult r1;
             CHK(pcg<double>(c, c->b, c->w, c->r, c->z, c->p, c->q, true, false, bref, c->opt.tol, c->opt.max_iter,
-                            -1, false, &r1));
+                            -1, false, &r1, rr0));
             local.iters[0] = r1.iters;
             local.relres = std::sqrt(r1.rr) / (bref > 0 ? bref : 1.0);
             local.relres0 = std::sqrt(r1.rr0) / (bref > 0 ? bref : 1.0);

@@ -92,6 +92,32 @@ int launch_residual(const T* b, const T* q, T* r, const uint8_t* mask, long N, i
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// r = P (b - (U0 G0 + U1 G1 + U2 G2)), G_c: 3 x N fields stored one after another;
+// partial sums of r.r.
+__global__ __launch_bounds__(kBlock) void k_lift_residual(const double* __restrict__ b, const double* __restrict__ G,
+                                                          double U0, double U1, double U2,
+                                                          const uint8_t* __restrict__ mask, long N, long n,
+                                                          double* __restrict__ r, double* partials)
+{
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double v = b[i] - (U0 * G[i] + U1 * G[n + i] + U2 * G[2 * n + i]);
+        if (mask[i % N]) v = 0;
+        r[i] = v;
+        acc += v * v;
+    }
+    const double s = block_sum_v(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+int launch_lift_residual(const double* b, const double* G, const double* U3, const uint8_t* mask, long N, double* r,
+                         double* partials, hipStream_t s)
+{
+    const long n = 3 * N;
+    hipLaunchKernelGGL(k_lift_residual, dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, G, U3[0], U3[1], U3[2], mask, N, n,
+                       r, partials);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axpby(T* out, const T* a, const T* b, double c, long n)
 {
