@@ -101,15 +101,14 @@ def run_variant(pb, opts, steps, warmup, label, net=None):
 
 
 def operator_rates(pb):
-    """Operator GVoxel/s (FP64 and FP32) with HIP events on the library's stream, and
-    per-pass event timings of the operator chain."""
+    """Operator GVoxel/s (FP64 and FP32) and per-pass times, from HIP events that the
+    library records between the passes on its own stream (nm_profile_passes)."""
     import torch
     from paper_2211_08263_amd import newmark as nmb
     N = pb.n_vox
     out = {}
     ctx = nmb.newmark_init_problem(pb, nmb.Options())
     try:
-        stream = torch.cuda.ExternalStream(nmb.get_stream(ctx))
         g = torch.Generator(device="cuda").manual_seed(7)
         for dt, label, rb in ((torch.float64, "fp64", 8), (torch.float32, "fp32", 4)):
             u = torch.randn(3 * N, device="cuda", dtype=torch.float64, generator=g).to(dt)
@@ -117,17 +116,10 @@ def operator_rates(pb):
             torch.cuda.synchronize()
             for _ in range(3):
                 nmb.apply_operator(ctx, u, Au)
-            times = []
-            for _ in range(20):
-                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
-                e0.record(stream)
-                nmb.apply_operator(ctx, u, Au)
-                e1.record(stream)
-                e1.synchronize()
-                times.append(e0.elapsed_time(e1))
-            times.sort()
-            med = times[len(times) // 2]
-            passes = nmb.profile_passes(ctx, 0, u, Au, reps=10)
+            runs = [nmb.profile_passes(ctx, 0, u, Au, reps=10) for _ in range(5)]
+            totals = sorted(sum(r.values()) for r in runs)
+            med = totals[len(totals) // 2]
+            passes = {k: sorted(r[k] for r in runs)[len(runs) // 2] for k in runs[0]}
             pre = nmb.profile_passes(ctx, 1, u, Au, reps=10)
             bpv = operator_bytes_per_voxel(rb)
             out[label] = {"apply_ms_median": med, "gvoxel_per_s": N / (med * 1e-3) / 1e9,

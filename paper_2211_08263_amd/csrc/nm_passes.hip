@@ -723,6 +723,9 @@ static inline int radix_x(int M) { return M >= 8 ? 8 : M; }
 #ifndef NM_STRESS_R64
 #define NM_STRESS_R64 4
 #endif
+#ifndef NM_STRESS_R32
+#define NM_STRESS_R32 4
+#endif
 
 int xfwd_blocks(int n1, long nlines)
 {
@@ -779,7 +782,9 @@ int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* ph
     const cx_t<T>* t = (const cx_t<T>*)tw;
     NM_SIZE_SWITCH(n1, {
         constexpr int M = NN / 2;
-        constexpr int R = sizeof(T) == 8 ? (M >= NM_STRESS_R64 ? NM_STRESS_R64 : M) : (M >= 8 ? 8 : M);
+        constexpr int RQ = sizeof(T) == 8 ? NM_STRESS_R64 : NM_STRESS_R32;
+        constexpr int R0 = M >= RQ ? RQ : M;
+        constexpr int R = R0 * 64 >= M ? R0 : M / 64; // a line stays inside one wavefront
         constexpr int G = M / R, LPB = kBlock / G;
         const int blocks = (int)((lpc + LPB - 1) / LPB);
         hipLaunchKernelGGL((k_xstress<T, NN, R>), dim3(blocks), dim3(kBlock), 0, s, (cx_t<T>*)spec, lay, phase,

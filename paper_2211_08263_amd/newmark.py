@@ -11,6 +11,15 @@ import os
 from dataclasses import dataclass
 from typing import Optional, Sequence
 
+# PyTorch bundles a HIP runtime under the same soname as the system one.  Importing
+# PyTorch before the library is loaded makes the library bind to that same runtime (one
+# device context, shared streams and events); loaded the other way round the process
+# would hold two runtimes and PyTorch would find no GPU.
+try:
+    import torch as _torch  # noqa: F401
+except ImportError:
+    _torch = None
+
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
@@ -61,6 +70,19 @@ class StepStats(C.Structure):
 _lib = None
 
 
+def hip_runtimes_loaded():
+    """Paths of the HIP runtime libraries mapped into this process (Linux)."""
+    paths = set()
+    try:
+        with open("/proc/self/maps") as f:
+            for line in f:
+                if "libamdhip64" in line:
+                    paths.add(line.split()[-1])
+    except OSError:
+        pass
+    return paths
+
+
 def load_library():
     """Load the built HIP library; raises if it has not been built."""
     global _lib
@@ -70,6 +92,10 @@ def load_library():
         raise RuntimeError("libnewmark.so is not built (run __graft_entry__.build() or "
                            "python paper_2211_08263_amd/build.py); there is no CPU fallback")
     L = C.CDLL(LIB_PATH)
+    runtimes = hip_runtimes_loaded()
+    if len(runtimes) > 1:
+        raise RuntimeError("two HIP runtimes are loaded in this process (%s); import torch before anything "
+                           "that loads the ROCm HIP runtime" % ", ".join(sorted(runtimes)))
     vp, i, d = C.c_void_p, C.c_int, C.c_double
     L.nm_newmark_init.argtypes = [C.POINTER(_Problem), C.POINTER(_Options), vp, C.POINTER(vp)]
     L.nm_newmark_step.argtypes = [vp, vp, i, C.POINTER(StepStats)]

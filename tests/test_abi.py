@@ -36,3 +36,11 @@ def test_binding_refuses_to_run_without_the_library(monkeypatch, tmp_path):
     monkeypatch.setattr(newmark, "LIB_PATH", str(tmp_path / "missing.so"))
     with pytest.raises(RuntimeError, match="not built"):
         newmark.load_library()
+
+
+def test_library_shares_the_hip_runtime_of_torch():
+    """One HIP runtime per process: the library binds to the one PyTorch loaded."""
+    from paper_2211_08263_amd import newmark as nmb
+    nmb.load_library()
+    rts = nmb.hip_runtimes_loaded()
+    assert len(rts) == 1, rts
