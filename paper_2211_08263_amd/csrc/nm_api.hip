@@ -366,8 +366,20 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
     int sweeps = 0, inner = 0;
     double rr = 0;
     for (;;) {
+        bool approx = false;
         if (sweeps == 0 && rr_known >= 0) {
             rr = rr_known;
+        } else if (sweeps == 0) {
+            // the first residual only seeds the first correction, whose own accuracy is
+            // about inner_tol, so the FP32 operator serves; every later residual (and the
+            // stopping test) is FP64
+            LCHK(c, launch_cast_d2f(c->d32, x, n, s));
+            CHK(apply_A<float>(c, c->d32, c->q32, c->mask));
+            LCHK(c, launch_residual_f32q(c->b, c->q32, c->r, c->mask, c->N, c->part_a, s));
+            LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+            CHK(read_scalars(c));
+            rr = c->hscal[S_RR];
+            approx = true;
         } else {
             CHK(apply_A<double>(c, x, c->q, c->mask));
             LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
@@ -377,7 +389,7 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
         }
         if (sweeps == 0 && st) st->relres0 = std::sqrt(rr) / bref;
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual in refinement sweep %d", sweeps);
-        if (std::sqrt(rr) <= c->opt.tol * bref) break;
+        if (!approx && std::sqrt(rr) <= c->opt.tol * bref) break;
         if (sweeps >= c->opt.max_sweeps)
             return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps (rel %.3g)", c->opt.tol,
                         sweeps, std::sqrt(rr) / bref);

@@ -23,6 +23,15 @@
 #include "nm_fft.h"
 #include "nm_passes.h"
 
+// Strain components whose loads the stress pass keeps in flight ahead of its transforms
+// (FP64 holds fewer: its registers limit the occupancy).
+#ifndef NM_STRESS_PF64
+#define NM_STRESS_PF64 2
+#endif
+#ifndef NM_STRESS_PF32
+#define NM_STRESS_PF32 6
+#endif
+
 namespace nm {
 
 // ---------------------------------------------------------------------------
@@ -282,12 +291,14 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
     const bool valid = line < (long)lay.n2 * lay.n3;
     const long off = lay.line(line), NS = lay.cs;
     LineAddr<R, (int)sizeof(V)> addr{ll * LP};
-    // issue every global load of the line (six strain spectra and the grain ids) before
-    // the first LDS exchange: the fences of the exchanges would otherwise hold each
-    // component's loads back until the previous component's transform is done
+    // keep the global loads of the next PF strain components in flight while a
+    // component is transformed: the fences of the LDS exchanges would otherwise hold
+    // each component's loads back until the previous transform is done
+    constexpr int PFQ = sizeof(T) == 8 ? NM_STRESS_PF64 : NM_STRESS_PF32;
+    constexpr int PF = PFQ < 6 ? PFQ : 6;
     V raw[6][R];
 #pragma unroll
-    for (int c = 0; c < 6; c++)
+    for (int c = 0; c < PF; c++)
 #pragma unroll
         for (int m = 0; m < R; m++) raw[c][m] = valid ? spec[c * NS + off + t + m * G] : V{0, 0};
     uint32_t phw[R];
@@ -302,6 +313,10 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
         V v[R];
 #pragma unroll
         for (int m = 0; m < R; m++) v[m] = raw[c][m];
+        if (c + PF < 6) {
+#pragma unroll
+            for (int m = 0; m < R; m++) raw[c + PF][m] = valid ? spec[(c + PF) * NS + off + t + m * G] : V{0, 0};
+        }
 #pragma unroll
         for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
         group_sync<true>();

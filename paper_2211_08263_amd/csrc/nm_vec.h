@@ -23,6 +23,9 @@ template <typename T> int launch_axpby(T* out, const T* a, const T* b, double c,
 int launch_cast_d2f(float* y, const double* x, long n, hipStream_t s);
 int launch_add_f2d(double* x, const float* d, long n, hipStream_t s);
 template <typename T> int launch_fill(T* x, T v, long n, hipStream_t s);
+// r = P (b - q) for an FP32 q (FP64 arithmetic), partial sums of r.r.
+int launch_residual_f32q(const double* b, const float* q, double* r, const uint8_t* mask, long N, double* partials,
+                         hipStream_t s);
 // r = P (b - sum_c U3[c] G_c) with the three Gamma lifting responses G (3 x (3 x N)),
 // partial sums of r.r (vec_blocks(3 N) of them).
 int launch_lift_residual(const double* b, const double* G, const double* U3, const uint8_t* mask, long N, double* r,

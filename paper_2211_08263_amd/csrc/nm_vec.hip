@@ -92,6 +92,29 @@ int launch_residual(const T* b, const T* q, T* r, const uint8_t* mask, long N, i
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// r = P (b - q) with an FP32 q, accumulated in FP64; partial sums of r.r.
+__global__ __launch_bounds__(kBlock) void k_residual_f32q(const double* __restrict__ b, const float* __restrict__ q,
+                                                          double* __restrict__ r, const uint8_t* __restrict__ mask,
+                                                          long N, long n, double* partials)
+{
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double v = b[i] - (double)q[i];
+        if (mask && mask[i % N]) v = 0;
+        r[i] = v;
+        acc += v * v;
+    }
+    const double s = block_sum_v(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+int launch_residual_f32q(const double* b, const float* q, double* r, const uint8_t* mask, long N, double* partials,
+                         hipStream_t s)
+{
+    const long n = 3 * N;
+    hipLaunchKernelGGL(k_residual_f32q, dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, q, r, mask, N, n, partials);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 // r = P (b - (U0 G0 + U1 G1 + U2 G2)), G_c: 3 x N fields stored one after another;
 // partial sums of r.r.
 __global__ __launch_bounds__(kBlock) void k_lift_residual(const double* __restrict__ b, const double* __restrict__ G,
