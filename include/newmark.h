@@ -138,7 +138,9 @@ int nm_pcg_solve(nm_ctx* ctx, const void* b_dev, void* x_dev, int masked, double
 int nm_get_state(const nm_ctx* ctx, double* u, double* v, double* a, double* F_gamma, int64_t* step);
 /* Restore a checkpoint taken by nm_get_state (u, v, a required). */
 int nm_set_state(nm_ctx* ctx, const double* u, const double* v, const double* a, int64_t step);
-/* Zero-copy device views of the state (3 x N doubles each). */
+/* Zero-copy device views of the state (3 x N doubles each), valid until the next
+ * step (steps swap the displacement buffers); writes through them are seen by the
+ * next step. */
 int nm_state_device_ptrs(nm_ctx* ctx, void** u, void** v, void** a);
 /* The Green matrix (d*n_gamma)^2, row major, before factorization; GREEN route only. */
 int nm_green_matrix(const nm_ctx* ctx, double* G);

@@ -69,6 +69,7 @@ struct nm_ctx {
     // Gamma buffers
     double* Ubuf = nullptr; // dim * max(ng, 1)
     double* lift = nullptr; // projected route: A e_c, e_c = unit component c on Gamma (3 x (3 x N))
+    bool pred_ready = false; // ut and b hold the predictor of the coming step
     double* gbuf = nullptr; // dim * max(ng, 1)
     std::vector<double> G, LU, F_last;
     std::vector<int> piv;
@@ -852,8 +853,11 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     std::vector<double> U3;
     CHK(upload_U(c, U_n, per_point, U3));
     auto t0 = std::chrono::steady_clock::now();
-    // predictor and right-hand side, eq. (Fourier_ND_b)
-    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    // predictor and right-hand side, eq. (Fourier_ND_b) (already formed by the previous
+    // step's corrector unless the state or b changed since)
+    if (!c->pred_ready)
+        LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    c->pred_ready = false;
     // initial guess
     double t_warm = 0;
     switch (c->opt.warm_start) {
@@ -947,10 +951,13 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
                 for (int j = 0; j < d; j++) c->F_last[d * pnt + j] = g3[3 * pnt + j] / c->sp.bdt2;
         }
     }
-    // corrector, then u <- u_n (pointer swap)
-    LCHK(c, launch_corrector(c->w, c->ut, c->v, c->a, n, c->dt, c->beta, c->gam, s));
+    // corrector, fused with the predictor and right-hand side of the next step; then
+    // u <- u_n (pointer swap)
+    LCHK(c, launch_corrector_predictor(c->w, c->ut, c->v, c->a, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta,
+                                       c->gam, s));
     std::swap(c->u, c->w);
     HIPCHK(c, hipStreamSynchronize(s));
+    c->pred_ready = true;
     c->step++;
     local.t_step_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     local.t_warm_ms = t_warm;
@@ -990,6 +997,7 @@ int nm_pcg_solve(nm_ctx* c, const void* b_dev, void* x_dev, int masked, double t
     if (!(tol > 0) || max_iter <= 0) return fail(c, NM_EINVAL, "bad tolerance or max_iter");
     double bref;
     // the projected reference norm reads c->b, so stage the right-hand side there
+    c->pred_ready = false;
     HIPCHK(c, hipMemcpyAsync(c->b, b_dev, 3 * c->N * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
     if (masked) {
         CHK(projected_bref(c, (const double*)x_dev, &bref));
@@ -1031,12 +1039,14 @@ int nm_set_state(nm_ctx* c, const double* u, const double* v, const double* a, i
     HIPCHK(c, hipMemcpy(c->v, v, bytes, hipMemcpyHostToDevice));
     HIPCHK(c, hipMemcpy(c->a, a, bytes, hipMemcpyHostToDevice));
     c->step = step;
+    c->pred_ready = false;
     return NM_OK;
 }
 
 int nm_state_device_ptrs(nm_ctx* c, void** u, void** v, void** a)
 {
     if (!c) return NM_EINVAL;
+    c->pred_ready = false; // the caller may write the state through these views
     if (u) *u = c->u;
     if (v) *v = c->v;
     if (a) *a = c->a;
@@ -1091,7 +1101,7 @@ int nm_ws_features(nm_ctx* c, void* feat_dev)
 int nm_ws_target(nm_ctx* c, void* target_dev)
 {
     if (!c || !c->feat || !target_dev) return fail(c, NM_EINVAL, "call nm_ws_attach first");
-    LCHK(c, nm::warm_target(warm_args(c), c->u, (float*)target_dev, c->stream));
+    LCHK(c, nm::warm_target(warm_args(c), c->a, c->sp.bdt2, (float*)target_dev, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     return NM_OK;
 }

@@ -30,7 +30,8 @@ struct WarmArgs {
 
 int warm_features(const WarmArgs& a, hipStream_t s);
 int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s);
-int warm_target(const WarmArgs& a, const double* unext, float* target, hipStream_t s);
+// target (u_next - u~)/s from the new acceleration: u_next - u~ = beta dt^2 a_next
+int warm_target(const WarmArgs& a, const double* anext, double bdt2, float* target, hipStream_t s);
 // Residual-norm training: y = scale * P net(feat) (FP64 SoA, Gamma voxels zero) ...
 int warm_residual_forward(nm_net* net, const WarmArgs& a, const uint16_t* feat, double scale, const uint8_t* mask,
                           double* y, hipStream_t s);

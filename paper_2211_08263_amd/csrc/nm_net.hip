@@ -472,14 +472,15 @@ __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ ut, 
         for (int c = 0; c < 3; c++) x0[c * N + v] = ut[c * N + v] + s * (double)pred[v * kPredStride + c];
 }
 
-// target = (u_next - u~) / s  as FP32 [N][4]
-__global__ __launch_bounds__(256) void k_target(const double* __restrict__ unext, const double* __restrict__ ut,
+// target = (u_next - u~) / s = beta dt^2 a_next / s  (the corrector's definition of
+// a_next), as FP32 [N][4]
+__global__ __launch_bounds__(256) void k_target(const double* __restrict__ anext, double bdt2,
                                                 const double* __restrict__ scale, float* __restrict__ target, long N)
 {
-    const double inv = scale[0] > 0.0 ? 1.0 / scale[0] : 0.0;
+    const double inv = scale[0] > 0.0 ? bdt2 / scale[0] : 0.0;
     for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x) {
 #pragma unroll
-        for (int c = 0; c < 3; c++) target[v * kPredStride + c] = (float)((unext[c * N + v] - ut[c * N + v]) * inv);
+        for (int c = 0; c < 3; c++) target[v * kPredStride + c] = (float)(anext[c * N + v] * inv);
         target[v * kPredStride + 3] = 0.f;
     }
 }
@@ -918,9 +919,9 @@ int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int warm_target(const WarmArgs& a, const double* unext, float* target, hipStream_t s)
+int warm_target(const WarmArgs& a, const double* anext, double bdt2, float* target, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_target, dim3(2048), dim3(256), 0, s, unext, a.ut, a.scale, target, a.N);
+    hipLaunchKernelGGL(k_target, dim3(2048), dim3(256), 0, s, anext, bdt2, a.scale, target, a.N);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

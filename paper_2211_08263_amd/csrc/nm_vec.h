@@ -45,6 +45,9 @@ int launch_predictor(const double* u, const double* v, const double* a, double* 
                      const uint16_t* phase, const double* rho, long N, int ncomp, double dt, double beta,
                      hipStream_t s);
 // Newmark corrector: an = (un - ut)/(beta dt^2); v += dt((1-g) a + g an); a = an
+int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
+                               const double* rho, long N, int ncomp, double dt, double beta, double gam,
+                               hipStream_t s);
 int launch_corrector(const double* un, const double* ut, double* v, double* a, long n, double dt, double beta,
                      double gam, hipStream_t s);
 // Initial acceleration from q = A u0: a0 = (rho u0 - q) / (beta dt^2 rho) = div(C : grad^s u0) / rho

@@ -124,7 +124,11 @@ __global__ __launch_bounds__(kBlock) void k_lift_residual(const double* __restri
 {
     double acc = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        double v = b[i] - (U0 * G[i] + U1 * G[n + i] + U2 * G[2 * n + i]);
+        // components with a zero prescribed value are skipped (their responses are not read)
+        double q = U0 != 0.0 ? U0 * G[i] : 0.0;
+        if (U1 != 0.0) q += U1 * G[n + i];
+        if (U2 != 0.0) q += U2 * G[2 * n + i];
+        double v = b[i] - q;
         if (mask[i % N]) v = 0;
         r[i] = v;
         acc += v * v;
@@ -277,6 +281,37 @@ __global__ __launch_bounds__(kBlock) void k_corrector(const double* __restrict__
         a[i] = an;
     }
 }
+// Corrector of this step fused with the predictor of the next one:
+// a_n = (u_n - u~)/(beta dt^2), v_n = v + dt((1 - gamma) a + gamma a_n), then
+// u~' = u_n + dt v_n + dt^2 (1/2 - beta) a_n and b' = rho u~' (ut and b overwritten).
+__global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __restrict__ un, double* __restrict__ ut,
+                                                                double* __restrict__ v, double* __restrict__ a,
+                                                                double* __restrict__ b,
+                                                                const uint16_t* __restrict__ phase,
+                                                                const double* __restrict__ rho, long N, long n,
+                                                                double dt, double inv_bdt2, double gam, double c2)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const double u = un[i];
+        const double an = (u - ut[i]) * inv_bdt2;
+        const double vn = v[i] + dt * ((1.0 - gam) * a[i] + gam * an);
+        v[i] = vn;
+        a[i] = an;
+        const double w = u + dt * vn + c2 * an;
+        ut[i] = w;
+        b[i] = rho[phase[i % N]] * w;
+    }
+}
+int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
+                               const double* rho, long N, int ncomp, double dt, double beta, double gam,
+                               hipStream_t s)
+{
+    const long n = N * ncomp;
+    hipLaunchKernelGGL(k_corrector_predictor, dim3(vec_blocks(n)), dim3(kBlock), 0, s, un, ut, v, a, b, phase, rho, N,
+                       n, dt, 1.0 / (beta * dt * dt), gam, dt * dt * (0.5 - beta));
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 int launch_corrector(const double* un, const double* ut, double* v, double* a, long n, double dt, double beta,
                      double gam, hipStream_t s)
 {
