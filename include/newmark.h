@@ -203,6 +203,10 @@ int nm_ws_attach(nm_ctx* ctx, nm_net* net);
 /* Between steps: features (device BF16 [N][32]) of the next step from the current
  * Newmark state (u_n, v_n, a_n); stores the scale s in the context. */
 int nm_ws_features(nm_ctx* ctx, void* feat_dev);
+/* The learned initial iterate x0 = u~ + s net(f) of the coming step (device FP64 SoA
+ * 3 x N; Gamma entries not yet replaced by U), as NM_WS_LEARNED computes it inside
+ * nm_newmark_step (the material share of the first layer cached per network version). */
+int nm_ws_predict(nm_ctx* ctx, void* x0_dev);
 /* After the following nm_newmark_step: the training target (u_{n+1} - u~) / s as
  * device FP32 [N][4]. */
 int nm_ws_target(nm_ctx* ctx, void* target_dev);

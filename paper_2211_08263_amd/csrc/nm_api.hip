@@ -82,6 +82,8 @@ struct nm_ctx {
     float* matf = nullptr;
     double* wscale = nullptr;
     double* wred = nullptr;
+    float* l0mat = nullptr;
+    unsigned long long l0mat_version = 0;
 };
 
 namespace {
@@ -202,7 +204,7 @@ template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa
     const void* tw = Prec<T>::tw(c);
     LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
     LCHK(c, launch_ypass<T>(-1, 3, c->lay, spec, tw, s));
-    LCHK(c, launch_zspec<T>(ZOP_PRECOND, c->sp, c->lay, spec, tw, s));
+    LCHK(c, launch_zprecond<T>(c->sp, c->lay, spec, tw, s));
     LCHK(c, launch_ypass<T>(+1, 3, c->lay, spec, tw, s));
     LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s));
     return NM_OK;
@@ -358,6 +360,10 @@ int lift_bref(nm_ctx* c, const double* U3, double* bref)
 }
 
 // Mixed precision: FP64 residual r = P(b - A x), FP32 PCG correction, x += d.
+// Residuals at most this many outer tolerances large are updated with the FP32 operator
+// applied to the correction instead of recomputed with the FP64 operator.
+constexpr double kSmallUpdate = 5e3;
+
 // rr_known >= 0: c->r already holds the first sweep's residual P (b - A x), r.r = rr_known.
 int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_known = -1.0)
 {
@@ -366,10 +372,20 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
     if (bref <= 0) bref = 1.0;
     int sweeps = 0, inner = 0;
     double rr = 0;
+    bool small_update = false; // the last correction is small enough for an FP32 residual update
     for (;;) {
         bool approx = false;
         if (sweeps == 0 && rr_known >= 0) {
             rr = rr_known;
+        } else if (small_update) {
+            // r <- r - P A d with the FP32 operator: |A d| is about |r|, at most kSmallUpdate
+            // tol b_ref, so its FP32 rounding (a few 1e-7 of |A d|) stays below 1e-2 tol b_ref
+            // and the stopping test still certifies the FP64 iterate
+            CHK(apply_A<float>(c, c->d32, c->q32, c->mask));
+            LCHK(c, launch_update_f32q(c->r, c->q32, c->mask, c->N, c->part_a, s));
+            LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+            CHK(read_scalars(c));
+            rr = c->hscal[S_RR];
         } else if (sweeps == 0) {
             // the first residual only seeds the first correction, whose own accuracy is
             // about inner_tol, so the FP32 operator serves; every later residual (and the
@@ -394,6 +410,7 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
         if (sweeps >= c->opt.max_sweeps)
             return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps (rel %.3g)", c->opt.tol,
                         sweeps, std::sqrt(rr) / bref);
+        small_update = !approx && std::sqrt(rr) <= kSmallUpdate * c->opt.tol * bref;
         LCHK(c, launch_cast_d2f(c->rhs32, c->r, n, s));
         LCHK(c, launch_fill<float>(c->d32, 0.0f, n, s));
         PcgResult pr;
@@ -564,7 +581,7 @@ template <typename T> int profile_impl(nm_ctx* c, int which, const T* in, T* out
         } else {
             rc |= launch_xfwd<T>(XF_PLAIN, c->n1, fa, tw, s) | mark();
             rc |= launch_ypass<T>(-1, 3, c->lay, spec, tw, s) | mark();
-            rc |= launch_zspec<T>(ZOP_PRECOND, c->sp, c->lay, spec, tw, s) | mark();
+            rc |= launch_zprecond<T>(c->sp, c->lay, spec, tw, s) | mark();
             rc |= launch_ypass<T>(+1, 3, c->lay, spec, tw, s) | mark();
             rc |= launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s) | mark();
         }
@@ -603,6 +620,8 @@ nm::WarmArgs warm_args(nm_ctx* c)
     a.red = c->wred;
     a.scale = c->wscale;
     a.feat = c->feat;
+    a.l0mat = c->l0mat;
+    a.l0mat_version = &c->l0mat_version;
     return a;
 }
 
@@ -1066,12 +1085,14 @@ int nm_profile_passes(nm_ctx* c, int which, const void* u_dev, void* out_dev, in
 int nm_ws_attach(nm_ctx* c, nm_net* net)
 {
     if (!c) return NM_EINVAL;
+    if (net != c->net) c->l0mat_version = 0; // versions of different networks are unrelated
     c->net = net;
     if (!net || c->feat) return NM_OK;
     CHK(dalloc(c, &c->feat, 32 * (size_t)c->N));
     CHK(dalloc(c, &c->matf, 22 * (size_t)c->nph));
     CHK(dalloc(c, &c->wscale, 1));
     CHK(dalloc(c, &c->wred, 512));
+    CHK(dalloc(c, &c->l0mat, 16 * (size_t)c->N));
     std::vector<double> C(21 * (size_t)c->nph), rho(c->nph);
     HIPCHK(c, hipMemcpy(C.data(), c->C64, C.size() * sizeof(double), hipMemcpyDeviceToHost));
     HIPCHK(c, hipMemcpy(rho.data(), c->rho64, rho.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -1094,6 +1115,17 @@ int nm_ws_features(nm_ctx* c, void* feat_dev)
     nm::WarmArgs a = warm_args(c);
     if (feat_dev) a.feat = (uint16_t*)feat_dev;
     LCHK(c, nm::warm_features(a, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    return NM_OK;
+}
+
+int nm_ws_predict(nm_ctx* c, void* x0_dev)
+{
+    if (!c || !c->net || !x0_dev) return fail(c, NM_EINVAL, "attach a network and pass x0");
+    hipStream_t s = c->stream;
+    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    int e = nm::warm_predict(c->net, warm_args(c), (double*)x0_dev, s);
+    if (e) return fail(c, e == -1 ? NM_EUNSUPPORTED : NM_EHIP, "warm-start network failed");
     HIPCHK(c, hipStreamSynchronize(s));
     return NM_OK;
 }

@@ -26,6 +26,8 @@ struct WarmArgs {
     double* red;           // >= 512 partial sums
     double* scale;         // one double: rms(u~ - u_n)
     uint16_t* feat;        // BF16 [N][32]
+    float* l0mat;          // FP32 [N][16]: material share of layer 0 (with its bias)
+    unsigned long long* l0mat_version; // network version l0mat was computed for (0: none)
 };
 
 int warm_features(const WarmArgs& a, hipStream_t s);

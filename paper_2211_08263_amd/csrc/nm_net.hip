@@ -32,6 +32,7 @@ constexpr int kFeat = 32;   // padded feature channels
 constexpr int kHid = 16;    // hidden channels (also the padded MFMA N)
 constexpr int kOutC = 3;    // predicted displacement components
 constexpr int kPredStride = 4;
+constexpr int kState = 9;   // state feature channels (u, dt v, dt^2 (1/2 - beta) a)
 
 __host__ __device__ inline uint16_t f2bf(float f)
 {
@@ -66,7 +67,8 @@ __device__ __forceinline__ long tap_voxel(int x, int y, int z, int t, const Grid
 //   X: BF16 [N][CINP], W: BF16 [27][16][CINP] (co padded to 16), bias FP32 [16].
 // Epilogues: EPI_BF16_ACT  -> BF16 [N][16], leaky ReLU
 //            EPI_F32       -> FP32 [N][ostride] (channels < cout), no activation
-//            EPI_BF16_DACT -> BF16 [N][16] times leaky'(Aprev) (backward data pass)
+//            EPI_BF16_DACT -> BF16 [N][16] times leaky'(aux), aux BF16 [N][16] (backward data pass)
+//            EPI_BF16_ACT_ADD -> BF16 [N][16], leaky ReLU of the sum with aux, FP32 [N][16]
 //
 // A block owns a 16 (x) by TY (y) column of voxels over ZC consecutive z planes.
 // It keeps three halo planes of the input ((TY + 2) x 18 voxels, all CINP
@@ -79,7 +81,7 @@ __device__ __forceinline__ long tap_voxel(int x, int y, int z, int t, const Grid
 // LDS plane layout: [kc][row][col][16 channels] BF16, so the 64 lanes of one
 // A-operand read cover 512 contiguous bytes.
 // ---------------------------------------------------------------------------
-enum { EPI_BF16_ACT = 0, EPI_F32 = 1, EPI_BF16_DACT = 2 };
+enum { EPI_BF16_ACT = 0, EPI_F32 = 1, EPI_BF16_DACT = 2, EPI_BF16_ACT_ADD = 3 };
 
 constexpr int kTX = 16;            // x extent of a block tile
 constexpr int kHX = kTX + 2;       // halo columns
@@ -131,7 +133,7 @@ template <int CINP> struct ConvK {
 template <int CINP, int EPI>
 __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X, const uint16_t* __restrict__ W,
                                                   const float* __restrict__ bias, void* __restrict__ Y,
-                                                  const uint16_t* __restrict__ Aprev, Grid g, int cout, int ostride,
+                                                  const void* __restrict__ aux, Grid g, int cout, int ostride,
                                                   int TY, int ZC)
 {
     constexpr int KC = CINP / 16;
@@ -224,11 +226,18 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
                 const int vv = lane >> 2, c0 = 4 * (lane & 3);
                 const float4 o4 = *(const float4*)&stg[wv][vv * 16 + c0];
                 float o[4] = {o4.x, o4.y, o4.z, o4.w};
-                if constexpr (EPI == EPI_BF16_ACT) {
+                if constexpr (EPI == EPI_BF16_ACT || EPI == EPI_BF16_ACT_ADD) {
+                    if constexpr (EPI == EPI_BF16_ACT_ADD) {
+                        const float4 ad = *(const float4*)((const float*)aux + (v0 + vv) * kHid + c0);
+                        o[0] += ad.x;
+                        o[1] += ad.y;
+                        o[2] += ad.z;
+                        o[3] += ad.w;
+                    }
 #pragma unroll
                     for (int c = 0; c < 4; c++) o[c] = o[c] > 0.f ? o[c] : kLeak * o[c];
                 } else {
-                    const uint64_t ap = *(const uint64_t*)(Aprev + (v0 + vv) * kHid + c0);
+                    const uint64_t ap = *(const uint64_t*)((const uint16_t*)aux + (v0 + vv) * kHid + c0);
 #pragma unroll
                     for (int c = 0; c < 4; c++) {
                         const float av = bf2f((uint16_t)(ap >> (16 * c)));
@@ -405,6 +414,16 @@ __global__ void k_pack(const float* __restrict__ W, int cin, int cout, int cinp,
     }
 }
 
+// Layer 0 restricted to the state channels (ci < 9) in the 16-channel forward layout
+// Wf0s[tap][16 (co)][16 (ci)]; W0 is [16][31][27].
+__global__ void k_pack_state(const float* __restrict__ W0, uint16_t* __restrict__ Wf0s)
+{
+    const int e = blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= 27 * 256) return;
+    const int ci = e % 16, co = (e / 16) % 16, t = e / 256;
+    Wf0s[e] = ci < kState ? f2bf(W0[((long)co * 31 + ci) * 27 + t]) : (uint16_t)0;
+}
+
 // ---------------------------------------------------------------------------
 // Features and prediction
 // ---------------------------------------------------------------------------
@@ -457,6 +476,53 @@ __global__ __launch_bounds__(256) void k_features(const double* __restrict__ u, 
         for (int c = 0; c < kFeat; c += 4) {
             uint64_t w = (uint64_t)f[c] | ((uint64_t)f[c + 1] << 16) | ((uint64_t)f[c + 2] << 32) |
                          ((uint64_t)f[c + 3] << 48);
+            *(uint64_t*)(X + i * kFeat + c) = w;
+        }
+    }
+}
+
+// Inference features, state part only: BF16 [N][16], channels 0..8 as in k_features, rest 0.
+__global__ __launch_bounds__(256) void k_features_state(const double* __restrict__ u, const double* __restrict__ v,
+                                                        const double* __restrict__ a, double dt, double c2, long N,
+                                                        const double* __restrict__ scale, uint16_t* __restrict__ X)
+{
+    const double inv = scale[0] > 0.0 ? 1.0 / scale[0] : 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+        uint16_t f[16];
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            f[c] = f2bf((float)(u[c * N + i] * inv));
+            f[3 + c] = f2bf((float)(dt * v[c * N + i] * inv));
+            f[6 + c] = f2bf((float)(c2 * a[c * N + i] * inv));
+        }
+#pragma unroll
+        for (int c = kState; c < 16; c++) f[c] = 0;
+#pragma unroll
+        for (int c = 0; c < 16; c += 4) {
+            const uint64_t w = (uint64_t)f[c] | ((uint64_t)f[c + 1] << 16) | ((uint64_t)f[c + 2] << 32) |
+                               ((uint64_t)f[c + 3] << 48);
+            *(uint64_t*)(X + i * 16 + c) = w;
+        }
+    }
+}
+
+// Material part of the features: BF16 [N][32] with the state channels zero.
+__global__ __launch_bounds__(256) void k_features_material(const uint16_t* __restrict__ phase,
+                                                           const float* __restrict__ matf, long N,
+                                                           uint16_t* __restrict__ X)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
+        uint16_t f[kFeat];
+#pragma unroll
+        for (int c = 0; c < kState; c++) f[c] = 0;
+        const float* mf = matf + 22 * (long)phase[i];
+#pragma unroll
+        for (int c = 0; c < 22; c++) f[kState + c] = f2bf(mf[c]);
+        f[31] = 0;
+#pragma unroll
+        for (int c = 0; c < kFeat; c += 4) {
+            const uint64_t w = (uint64_t)f[c] | ((uint64_t)f[c + 1] << 16) | ((uint64_t)f[c + 2] << 32) |
+                               ((uint64_t)f[c + 3] << 48);
             *(uint64_t*)(X + i * kFeat + c) = w;
         }
     }
@@ -519,29 +585,23 @@ __global__ __launch_bounds__(256) void k_dz_soa(const double* __restrict__ g, do
 // Host side
 // ---------------------------------------------------------------------------
 static int launch_conv(int cinp, int epi, const uint16_t* X, const uint16_t* W, const float* bias, void* Y,
-                       const uint16_t* Aprev, const Grid& g, int cout, int ostride, hipStream_t s)
+                       const void* aux, const Grid& g, int cout, int ostride, hipStream_t s)
 {
     // tiles: 16 x TY x ZC voxels per block (grid dimensions are powers of two, n1 >= 16)
     const int TY = g.n2 < kMaxTY ? g.n2 : kMaxTY;
     const int ZC = g.n3 < 16 ? g.n3 : 16;
     const dim3 grid(g.n1 / kTX, g.n2 / TY, g.n3 / ZC);
     if (g.n1 % kTX) return -1;
-    if (cinp == 32 && epi == EPI_BF16_ACT)
-        hipLaunchKernelGGL((k_conv_fwd<32, EPI_BF16_ACT>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
-                           ostride, TY, ZC);
-    else if (cinp == 32 && epi == EPI_F32)
-        hipLaunchKernelGGL((k_conv_fwd<32, EPI_F32>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout, ostride,
-                           TY, ZC);
-    else if (cinp == 16 && epi == EPI_BF16_ACT)
-        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_ACT>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
-                           ostride, TY, ZC);
-    else if (cinp == 16 && epi == EPI_F32)
-        hipLaunchKernelGGL((k_conv_fwd<16, EPI_F32>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout, ostride,
-                           TY, ZC);
-    else if (cinp == 16 && epi == EPI_BF16_DACT)
-        hipLaunchKernelGGL((k_conv_fwd<16, EPI_BF16_DACT>), grid, dim3(256), 0, s, X, W, bias, Y, Aprev, g, cout,
-                           ostride, TY, ZC);
+#define NM_CONV_LAUNCH(CI, EP)                                                                                         \
+    hipLaunchKernelGGL((k_conv_fwd<CI, EP>), grid, dim3(256), 0, s, X, W, bias, Y, aux, g, cout, ostride, TY, ZC)
+    if (cinp == 32 && epi == EPI_BF16_ACT) NM_CONV_LAUNCH(32, EPI_BF16_ACT);
+    else if (cinp == 32 && epi == EPI_F32) NM_CONV_LAUNCH(32, EPI_F32);
+    else if (cinp == 16 && epi == EPI_BF16_ACT) NM_CONV_LAUNCH(16, EPI_BF16_ACT);
+    else if (cinp == 16 && epi == EPI_F32) NM_CONV_LAUNCH(16, EPI_F32);
+    else if (cinp == 16 && epi == EPI_BF16_DACT) NM_CONV_LAUNCH(16, EPI_BF16_DACT);
+    else if (cinp == 16 && epi == EPI_BF16_ACT_ADD) NM_CONV_LAUNCH(16, EPI_BF16_ACT_ADD);
     else return -1;
+#undef NM_CONV_LAUNCH
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -581,6 +641,8 @@ struct nm_net {
     float *p = nullptr, *gr = nullptr, *m = nullptr, *v = nullptr; // device FP32
     uint16_t* wf[4] = {};                                         // forward BF16
     uint16_t* wb[4] = {};                                         // backward-data BF16
+    uint16_t* wf0s = nullptr; // layer 0 restricted to the 9 state channels, 16-channel layout
+    unsigned long long version = 0; // bumped whenever the weights change
     long step = 0;
     // workspace (grown on demand)
     long capN = 0;
@@ -611,6 +673,8 @@ static int net_pack(nm_net* n, hipStream_t s)
         hipLaunchKernelGGL(k_pack, dim3((tot + 255) / 256), dim3(256), 0, s, n->p + n->off[l], n->cin[l],
                            n->cout[l], n->cinp[l], n->wf[l], l > 0 ? n->wb[l] : nullptr);
     }
+    hipLaunchKernelGGL(k_pack_state, dim3(27), dim3(256), 0, s, n->p + n->off[0], n->wf0s);
+    n->version++;
     return hipGetLastError() == hipSuccess ? NM_OK : NM_EHIP;
 }
 
@@ -661,6 +725,7 @@ int nm_net_create(unsigned long long seed, nm_net** out)
         st |= net_alloc((void**)&n->wf[l], 27 * 16 * n->cinp[l] * 2, nullptr);
         st |= net_alloc((void**)&n->wb[l], 27 * 256 * 2, nullptr);
     }
+    st |= net_alloc((void**)&n->wf0s, 27 * 256 * 2, nullptr);
     if (st != NM_OK || hipHostMalloc((void**)&n->hred, 8 * sizeof(double), hipHostMallocDefault) != hipSuccess) {
         nm_net_destroy(n);
         return NM_ENOMEM;
@@ -687,6 +752,7 @@ void nm_net_destroy(nm_net* n)
         if (n->wf[l]) (void)hipFree(n->wf[l]);
         if (n->wb[l]) (void)hipFree(n->wb[l]);
     }
+    if (n->wf0s) (void)hipFree(n->wf0s);
     for (void* q : n->ws_allocs) (void)hipFree(q);
     if (n->hred) (void)hipHostFree(n->hred);
     delete n;
@@ -908,13 +974,38 @@ int warm_features(const WarmArgs& a, hipStream_t s)
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// Inference inside the solver.  The 22 material channels of the features do not change
+// from step to step, so their share of layer 0 (with its bias) is computed once per
+// network version and problem into l0mat (FP32 [N][16]); each step then convolves only
+// the 9 state channels (16-channel layout) and adds l0mat before the activation.
 int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
 {
     Grid g{a.n1, a.n2, a.n3, a.N};
     int n3[3] = {a.n1, a.n2, a.n3};
     if (check_grid(n3) != NM_OK) return -1;
-    if (warm_features(a, s)) return -2;
-    if (net_forward(net, g, a.feat, s) != NM_OK) return -2;
+    if (net_workspace(net, g.N) != NM_OK) return -2;
+    if (*a.l0mat_version != net->version) {
+        hipLaunchKernelGGL(k_features_material, dim3(2048), dim3(256), 0, s, a.phase, a.matf, a.N, a.feat);
+        const float* b0 = net->p + net->off[0] + layer_w(net, 0);
+        if (launch_conv(32, EPI_F32, a.feat, net->wf[0], b0, a.l0mat, nullptr, g, 16, 16, s)) return -2;
+        *a.l0mat_version = net->version;
+    }
+    const long n = 3 * a.N;
+    hipLaunchKernelGGL(k_incr_norm, dim3(512), dim3(256), 0, s, a.ut, a.u, n, a.red);
+    hipLaunchKernelGGL(k_sum_scale, dim3(1), dim3(64), 0, s, a.red, 512, n, a.scale);
+    hipLaunchKernelGGL(k_features_state, dim3(2048), dim3(256), 0, s, a.u, a.v, a.a, a.dt, a.c2, a.N, a.scale,
+                       a.feat);
+    if (launch_conv(16, EPI_BF16_ACT_ADD, a.feat, net->wf0s, nullptr, net->act[1], a.l0mat, g, 16, 16, s)) return -2;
+    for (int l = 1; l < net->L; l++) {
+        const float* b = net->p + net->off[l] + layer_w(net, l);
+        int e;
+        if (l < net->L - 1)
+            e = launch_conv(16, EPI_BF16_ACT, net->act[l], net->wf[l], b, net->act[l + 1], nullptr, g, 16, 16, s);
+        else
+            e = launch_conv(16, EPI_F32, net->act[l], net->wf[l], b, net->pred, nullptr, g, net->cout[l], kPredStride,
+                            s);
+        if (e) return -2;
+    }
     hipLaunchKernelGGL(k_predict, dim3(2048), dim3(256), 0, s, a.ut, net->pred, a.scale, x0, a.N);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }

@@ -39,8 +39,6 @@ struct SpecLayout {
 enum XFwdMode { XF_PLAIN = 0, XF_PUPDATE = 1, XF_UPDATE = 2 };
 // Fused stage after the x-direction complex-to-real transform.
 enum XInvMode { XI_PLAIN = 0, XI_OPERATOR = 1, XI_PRECOND = 2 };
-// Pointwise operator applied between the forward and inverse z transforms.
-enum ZOp { ZOP_GRAD = 0, ZOP_DIV = 1, ZOP_PRECOND = 2 };
 // Axis-wise derivative stages of the operator on x-spectral (kx, y, z) data:
 //   YOP_DERIV : S[3+j] = D_y S[j], j < 3
 //   ZOP_STRAIN: S2 = Voigt strain (eps11, eps22, eps33, g23, g13, g12) / n1 from
@@ -96,8 +94,8 @@ int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const vo
 template <typename T>
 int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, void* S2, const void* tw,
                  hipStream_t s);
-// In-place z-forward, pointwise operator, z-inverse.
+// Preconditioner z pass in place: z-forward, (beta dt^2 K + rhobar I)^-1, z-inverse.
 template <typename T>
-int launch_zspec(int op, const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s);
+int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s);
 
 } // namespace nm

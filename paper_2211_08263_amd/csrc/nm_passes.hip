@@ -413,9 +413,13 @@ template <typename T> struct ZOps {
     static __device__ __forceinline__ V iscale(V a, T s) { return V{-a.y * s, a.x * s}; }
 };
 
-template <typename T, int L, int R, int OP, int BLK, int TXC>
-__global__ __launch_bounds__(BLK) void k_zspec(cx_t<T>* __restrict__ data, long NS, long colstride, int TXr,
-                                               SpecParams sp, const cx_t<T>* __restrict__ tw)
+// Preconditioner z pass: forward z transforms of the three components, the pointwise
+// inverse of beta dt^2 K(xi) + rhobar I (K_ij = Cbar_ikjm xi_k xi_m, eqs. (precond),
+// (acous)) scaled by 1 / (n1 n2 n3), inverse z transforms.  Columns of TX kx bins
+// at one ky; data in place.
+template <typename T, int L, int R, int BLK, int TXC>
+__global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, long NS, long colstride, int TXr,
+                                                  SpecParams sp, const cx_t<T>* __restrict__ tw)
 {
     using V = cx_t<T>;
     constexpr int G = L / R;
@@ -436,152 +440,81 @@ __global__ __launch_bounds__(BLK) void k_zspec(cx_t<T>* __restrict__ data, long 
 #pragma unroll
     for (int m = 0; m < R; m++) xi3[m] = (T)(sp.k3 * freq_index(t + m * G, sp.n3));
 
-    if constexpr (OP == ZOP_GRAD || OP == ZOP_PRECOND) {
-        V u[3][R];
+    V u[3][R];
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+#pragma unroll
+        for (int m = 0; m < R; m++) u[j][m] = col[j * NS + (long)(t + m * G) * colstride];
+        group_fft<L, R, -1>(u[j], t, lds, addr, twL);
+    }
+    T C[6][6];
+    {
+        int o = 0;
+#pragma unroll
+        for (int a = 0; a < 6; a++)
+#pragma unroll
+            for (int b = a; b < 6; b++) {
+                C[a][b] = (T)sp.Cbar[o];
+                C[b][a] = (T)sp.Cbar[o];
+                o++;
+            }
+    }
+    const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const T x1 = xi1, x2 = xi2, x3 = xi3[m];
+        // K = N(xi)^T Cbar N(xi) with N the Voigt strain of a plane wave
+        T CN[6][3];
+#pragma unroll
+        for (int a = 0; a < 6; a++) {
+            CN[a][0] = C[a][0] * x1 + C[a][4] * x3 + C[a][5] * x2;
+            CN[a][1] = C[a][1] * x2 + C[a][3] * x3 + C[a][5] * x1;
+            CN[a][2] = C[a][2] * x3 + C[a][3] * x2 + C[a][4] * x1;
+        }
+        T K[3][3];
 #pragma unroll
         for (int j = 0; j < 3; j++) {
-#pragma unroll
-            for (int m = 0; m < R; m++) u[j][m] = col[j * NS + (long)(t + m * G) * colstride];
-            group_fft<L, R, -1>(u[j], t, lds, addr, twL);
+            K[0][j] = bdt2 * (x1 * CN[0][j] + x3 * CN[4][j] + x2 * CN[5][j]);
+            K[1][j] = bdt2 * (x2 * CN[1][j] + x3 * CN[3][j] + x1 * CN[5][j]);
+            K[2][j] = bdt2 * (x3 * CN[2][j] + x2 * CN[3][j] + x1 * CN[4][j]);
         }
-        if constexpr (OP == ZOP_GRAD) {
-            const T s = (T)sp.inv_ntot;
-#pragma unroll
-            for (int e = 0; e < 6; e++) {
-                V w[R];
-#pragma unroll
-                for (int m = 0; m < R; m++) {
-                    const T x3 = xi3[m];
-                    V a;
-                    switch (e) {
-                    case 0: a = cscale(u[0][m], xi1); break;
-                    case 1: a = cscale(u[1][m], xi2); break;
-                    case 2: a = cscale(u[2][m], x3); break;
-                    case 3: a = cadd(cscale(u[1][m], x3), cscale(u[2][m], xi2)); break;
-                    case 4: a = cadd(cscale(u[0][m], x3), cscale(u[2][m], xi1)); break;
-                    default: a = cadd(cscale(u[0][m], xi2), cscale(u[1][m], xi1)); break;
-                    }
-                    w[m] = ZOps<T>::iscale(a, s);
-                }
-                group_fft<L, R, +1>(w, t, lds, addr, twL);
-#pragma unroll
-                for (int m = 0; m < R; m++) col[e * NS + (long)(t + m * G) * colstride] = w[m];
-            }
+        K[0][0] += rb;
+        K[1][1] += rb;
+        K[2][2] += rb;
+        V z0, z1, z2;
+        if (sp.dim == 2) {
+            const T det = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+            const T id = s / det;
+            z0 = cscale(csub(cscale(u[0][m], K[1][1]), cscale(u[1][m], K[0][1])), id);
+            z1 = cscale(csub(cscale(u[1][m], K[0][0]), cscale(u[0][m], K[1][0])), id);
+            z2 = V{0, 0};
         } else {
-            // (beta dt^2 K(xi) + rhobar I)^-1, K = N(xi)^T Cbar N(xi)
-            T C[6][6];
-            {
-                int o = 0;
-#pragma unroll
-                for (int a = 0; a < 6; a++)
-#pragma unroll
-                    for (int b = a; b < 6; b++) {
-                        C[a][b] = (T)sp.Cbar[o];
-                        C[b][a] = (T)sp.Cbar[o];
-                        o++;
-                    }
-            }
-            const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
-#pragma unroll
-            for (int m = 0; m < R; m++) {
-                const T x1 = xi1, x2 = xi2, x3 = xi3[m];
-                T CN[6][3];
-#pragma unroll
-                for (int a = 0; a < 6; a++) {
-                    CN[a][0] = C[a][0] * x1 + C[a][4] * x3 + C[a][5] * x2;
-                    CN[a][1] = C[a][1] * x2 + C[a][3] * x3 + C[a][5] * x1;
-                    CN[a][2] = C[a][2] * x3 + C[a][3] * x2 + C[a][4] * x1;
-                }
-                T K[3][3];
-#pragma unroll
-                for (int j = 0; j < 3; j++) {
-                    K[0][j] = bdt2 * (x1 * CN[0][j] + x3 * CN[4][j] + x2 * CN[5][j]);
-                    K[1][j] = bdt2 * (x2 * CN[1][j] + x3 * CN[3][j] + x1 * CN[5][j]);
-                    K[2][j] = bdt2 * (x3 * CN[2][j] + x2 * CN[3][j] + x1 * CN[4][j]);
-                }
-                K[0][0] += rb;
-                K[1][1] += rb;
-                K[2][2] += rb;
-                V z0, z1, z2;
-                if (sp.dim == 2) {
-                    const T det = K[0][0] * K[1][1] - K[0][1] * K[1][0];
-                    const T id = s / det;
-                    z0 = cscale(csub(cscale(u[0][m], K[1][1]), cscale(u[1][m], K[0][1])), id);
-                    z1 = cscale(csub(cscale(u[1][m], K[0][0]), cscale(u[0][m], K[1][0])), id);
-                    z2 = V{0, 0};
-                } else {
-                    // inverse of the symmetric 3x3 by cofactors
-                    const T c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
-                    const T c01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
-                    const T c02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
-                    const T c11 = K[0][0] * K[2][2] - K[0][2] * K[2][0];
-                    const T c12 = K[0][2] * K[1][0] - K[0][0] * K[1][2];
-                    const T c22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
-                    const T det = K[0][0] * c00 + K[0][1] * (K[1][2] * K[2][0] - K[1][0] * K[2][2]) +
-                                  K[0][2] * (K[1][0] * K[2][1] - K[1][1] * K[2][0]);
-                    const T id = s / det;
-                    const V r0 = u[0][m], r1 = u[1][m], r2 = u[2][m];
-                    z0 = cscale(cadd(cadd(cscale(r0, c00), cscale(r1, c01)), cscale(r2, c02)), id);
-                    z1 = cscale(cadd(cadd(cscale(r0, c01), cscale(r1, c11)), cscale(r2, c12)), id);
-                    z2 = cscale(cadd(cadd(cscale(r0, c02), cscale(r1, c12)), cscale(r2, c22)), id);
-                }
-                u[0][m] = z0;
-                u[1][m] = z1;
-                u[2][m] = z2;
-            }
-#pragma unroll
-            for (int j = 0; j < 3; j++) {
-                group_fft<L, R, +1>(u[j], t, lds, addr, twL);
-#pragma unroll
-                for (int m = 0; m < R; m++) col[j * NS + (long)(t + m * G) * colstride] = u[j][m];
-            }
+            // inverse of the symmetric 3x3 by cofactors
+            const T c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
+            const T c01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
+            const T c02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
+            const T c11 = K[0][0] * K[2][2] - K[0][2] * K[2][0];
+            const T c12 = K[0][2] * K[1][0] - K[0][0] * K[1][2];
+            const T c22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
+            const T det = K[0][0] * c00 + K[0][1] * (K[1][2] * K[2][0] - K[1][0] * K[2][2]) +
+                          K[0][2] * (K[1][0] * K[2][1] - K[1][1] * K[2][0]);
+            const T id = s / det;
+            const V r0 = u[0][m], r1 = u[1][m], r2 = u[2][m];
+            z0 = cscale(cadd(cadd(cscale(r0, c00), cscale(r1, c01)), cscale(r2, c02)), id);
+            z1 = cscale(cadd(cadd(cscale(r0, c01), cscale(r1, c11)), cscale(r2, c12)), id);
+            z2 = cscale(cadd(cadd(cscale(r0, c02), cscale(r1, c12)), cscale(r2, c22)), id);
         }
-    } else {
-        // divergence: q_j = -beta dt^2 i xi_k sigma_jk, accumulated over the 6 Voigt components
-        V q[3][R];
+        u[0][m] = z0;
+        u[1][m] = z1;
+        u[2][m] = z2;
+    }
 #pragma unroll
-        for (int j = 0; j < 3; j++)
+    for (int j = 0; j < 3; j++) {
+        group_fft<L, R, +1>(u[j], t, lds, addr, twL);
 #pragma unroll
-            for (int m = 0; m < R; m++) q[j][m] = V{0, 0};
-        const T s = (T)(-sp.bdt2 * sp.inv_ntot);
-#pragma unroll
-        for (int e = 0; e < 6; e++) {
-            V w[R];
-#pragma unroll
-            for (int m = 0; m < R; m++) w[m] = col[e * NS + (long)(t + m * G) * colstride];
-            group_fft<L, R, -1>(w, t, lds, addr, twL);
-#pragma unroll
-            for (int m = 0; m < R; m++) {
-                const V is = ZOps<T>::iscale(w[m], s);
-                const T x3 = xi3[m];
-                switch (e) {
-                case 0: q[0][m] = cadd(q[0][m], cscale(is, xi1)); break;
-                case 1: q[1][m] = cadd(q[1][m], cscale(is, xi2)); break;
-                case 2: q[2][m] = cadd(q[2][m], cscale(is, x3)); break;
-                case 3:
-                    q[1][m] = cadd(q[1][m], cscale(is, x3));
-                    q[2][m] = cadd(q[2][m], cscale(is, xi2));
-                    break;
-                case 4:
-                    q[0][m] = cadd(q[0][m], cscale(is, x3));
-                    q[2][m] = cadd(q[2][m], cscale(is, xi1));
-                    break;
-                default:
-                    q[0][m] = cadd(q[0][m], cscale(is, xi2));
-                    q[1][m] = cadd(q[1][m], cscale(is, xi1));
-                    break;
-                }
-            }
-        }
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            group_fft<L, R, +1>(q[j], t, lds, addr, twL);
-#pragma unroll
-            for (int m = 0; m < R; m++) col[j * NS + (long)(t + m * G) * colstride] = q[j][m];
-        }
+        for (int m = 0; m < R; m++) col[j * NS + (long)(t + m * G) * colstride] = u[j][m];
     }
 }
-
 
 // ---------------------------------------------------------------------------
 // Axis-wise derivative stages of the operator (see ColOp).  Data are x-spectral
@@ -857,21 +790,15 @@ int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const vo
 }
 
 template <typename T, int L, int BLK, int TXC>
-static void zspec_dispatch(int op, dim3 grid, dim3 block, hipStream_t s, cx_t<T>* spec, const SpecLayout& lay,
-                           int TX, const SpecParams& sp, const cx_t<T>* t)
+static void zprecond_dispatch(dim3 grid, dim3 block, hipStream_t s, cx_t<T>* spec, const SpecLayout& lay, int TX,
+                              const SpecParams& sp, const cx_t<T>* t)
 {
     constexpr int R = zspec_radix<T, L>();
-    if (op == ZOP_GRAD)
-        hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_GRAD, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX, sp, t);
-    else if (op == ZOP_DIV)
-        hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_DIV, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX, sp, t);
-    else
-        hipLaunchKernelGGL((k_zspec<T, L, R, ZOP_PRECOND, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX,
-                           sp, t);
+    hipLaunchKernelGGL((k_zprecond<T, L, R, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX, sp, t);
 }
 
 template <typename T>
-int launch_zspec(int op, const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s)
+int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s)
 {
     const int M = sp.n1 / 2;
     const cx_t<T>* t = (const cx_t<T>*)tw;
@@ -879,15 +806,15 @@ int launch_zspec(int op, const SpecParams& sp, const SpecLayout& lay, void* spec
     constexpr int BLK = zspec_block<T>();
     if (sp.n3 == 1) {
         const int TX = M < BLK ? M : BLK;
-        zspec_dispatch<T, 1, BLK, 0>(op, dim3(M / TX, sp.n2), dim3(TX), s, d, lay, TX, sp, t);
+        zprecond_dispatch<T, 1, BLK, 0>(dim3(M / TX, sp.n2), dim3(TX), s, d, lay, TX, sp, t);
     } else {
         NM_SIZE_SWITCH(sp.n3, {
             constexpr int G = NN / zspec_radix<T, NN>();
             constexpr int TXP = BLK / G;
             if (M >= TXP)
-                zspec_dispatch<T, NN, BLK, TXP>(op, dim3(M / TXP, sp.n2), dim3(TXP * G), s, d, lay, TXP, sp, t);
+                zprecond_dispatch<T, NN, BLK, TXP>(dim3(M / TXP, sp.n2), dim3(TXP * G), s, d, lay, TXP, sp, t);
             else
-                zspec_dispatch<T, NN, BLK, 0>(op, dim3(1, sp.n2), dim3(M * G), s, d, lay, M, sp, t);
+                zprecond_dispatch<T, NN, BLK, 0>(dim3(1, sp.n2), dim3(M * G), s, d, lay, M, sp, t);
         })
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -959,7 +886,7 @@ int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, v
     template int launch_xstress<T>(int, void*, const SpecLayout&, const uint16_t*, const void*, const void*,          \
                                    hipStream_t);                                                                       \
     template int launch_ypass<T>(int, int, const SpecLayout&, void*, const void*, hipStream_t);                        \
-    template int launch_zspec<T>(int, const SpecParams&, const SpecLayout&, void*, const void*, hipStream_t);        \
+    template int launch_zprecond<T>(const SpecParams&, const SpecLayout&, void*, const void*, hipStream_t);          \
     template int launch_colop<T>(int, const SpecParams&, const SpecLayout&, void*, void*, const void*, hipStream_t);
 NM_INST(double)
 NM_INST(float)

@@ -26,6 +26,8 @@ template <typename T> int launch_fill(T* x, T v, long n, hipStream_t s);
 // r = P (b - q) for an FP32 q (FP64 arithmetic), partial sums of r.r.
 int launch_residual_f32q(const double* b, const float* q, double* r, const uint8_t* mask, long N, double* partials,
                          hipStream_t s);
+// r <- P (r - q) in place for an FP32 q (FP64 arithmetic), partial sums of r.r.
+int launch_update_f32q(double* r, const float* q, const uint8_t* mask, long N, double* partials, hipStream_t s);
 // r = P (b - sum_c U3[c] G_c) with the three Gamma lifting responses G (3 x (3 x N)),
 // partial sums of r.r (vec_blocks(3 N) of them).
 int launch_lift_residual(const double* b, const double* G, const double* U3, const uint8_t* mask, long N, double* r,
@@ -44,12 +46,11 @@ int launch_gather_gamma(double* out, const double* x, const int64_t* gidx, long 
 int launch_predictor(const double* u, const double* v, const double* a, double* ut, double* b,
                      const uint16_t* phase, const double* rho, long N, int ncomp, double dt, double beta,
                      hipStream_t s);
-// Newmark corrector: an = (un - ut)/(beta dt^2); v += dt((1-g) a + g an); a = an
+// Newmark corrector (an = (un - ut)/(beta dt^2); v += dt((1-g) a + g an); a = an) fused
+// with the next predictor (ut = un + dt v + dt^2 (1/2 - beta) a) and b = rho ut.
 int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
                                const double* rho, long N, int ncomp, double dt, double beta, double gam,
                                hipStream_t s);
-int launch_corrector(const double* un, const double* ut, double* v, double* a, long n, double dt, double beta,
-                     double gam, hipStream_t s);
 // Initial acceleration from q = A u0: a0 = (rho u0 - q) / (beta dt^2 rho) = div(C : grad^s u0) / rho
 int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* phase, const double* rho, long N,
                   int ncomp, double bdt2, hipStream_t s);

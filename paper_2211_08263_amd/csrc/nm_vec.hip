@@ -115,6 +115,28 @@ int launch_residual_f32q(const double* b, const float* q, double* r, const uint8
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// r <- P (r - q) in place for an FP32 q (FP64 arithmetic); partial sums of r.r.
+__global__ __launch_bounds__(kBlock) void k_update_f32q(double* r, const float* __restrict__ q,
+                                                        const uint8_t* __restrict__ mask, long N, long n,
+                                                        double* partials)
+{
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        double v = r[i] - (double)q[i];
+        if (mask && mask[i % N]) v = 0;
+        r[i] = v;
+        acc += v * v;
+    }
+    const double s = block_sum_v(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+int launch_update_f32q(double* r, const float* q, const uint8_t* mask, long N, double* partials, hipStream_t s)
+{
+    const long n = 3 * N;
+    hipLaunchKernelGGL(k_update_f32q, dim3(vec_blocks(n)), dim3(kBlock), 0, s, r, q, mask, N, n, partials);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 // r = P (b - (U0 G0 + U1 G1 + U2 G2)), G_c: 3 x N fields stored one after another;
 // partial sums of r.r.
 __global__ __launch_bounds__(kBlock) void k_lift_residual(const double* __restrict__ b, const double* __restrict__ G,
@@ -271,16 +293,6 @@ int launch_predictor(const double* u, const double* v, const double* a, double* 
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-__global__ __launch_bounds__(kBlock) void k_corrector(const double* __restrict__ un, const double* __restrict__ ut,
-                                                      double* __restrict__ v, double* __restrict__ a, long n,
-                                                      double dt, double inv_bdt2, double gam)
-{
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double an = (un[i] - ut[i]) * inv_bdt2;
-        v[i] = v[i] + dt * ((1.0 - gam) * a[i] + gam * an);
-        a[i] = an;
-    }
-}
 // Corrector of this step fused with the predictor of the next one:
 // a_n = (u_n - u~)/(beta dt^2), v_n = v + dt((1 - gamma) a + gamma a_n), then
 // u~' = u_n + dt v_n + dt^2 (1/2 - beta) a_n and b' = rho u~' (ut and b overwritten).
@@ -312,13 +324,6 @@ int launch_corrector_predictor(const double* un, double* ut, double* v, double* 
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-int launch_corrector(const double* un, const double* ut, double* v, double* a, long n, double dt, double beta,
-                     double gam, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_corrector, dim3(vec_blocks(n)), dim3(kBlock), 0, s, un, ut, v, a, n, dt,
-                       1.0 / (beta * dt * dt), gam);
-    return hipGetLastError() == hipSuccess ? 0 : -2;
-}
 
 __global__ __launch_bounds__(kBlock) void k_accel0(double* a, const double* u0, const double* q,
                                                    const uint16_t* phase, const double* rho, long N, long n,

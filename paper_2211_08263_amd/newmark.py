@@ -35,7 +35,7 @@ EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_preco
             "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream", "nm_profile_passes",
             "nm_net_create", "nm_net_destroy", "nm_net_num_params", "nm_net_get_params", "nm_net_set_params",
             "nm_net_forward", "nm_net_train_step", "nm_net_gradients", "nm_conv3d_bf16", "nm_ws_attach",
-            "nm_ws_features", "nm_ws_target", "nm_ws_residual_sample", "nm_ws_train_residual",
+            "nm_ws_features", "nm_ws_target", "nm_ws_predict", "nm_ws_residual_sample", "nm_ws_train_residual",
             "nm_last_error", "nm_destroy")
 
 
@@ -121,6 +121,7 @@ def load_library():
     L.nm_ws_attach.argtypes = [vp, vp]
     L.nm_ws_features.argtypes = [vp, vp]
     L.nm_ws_target.argtypes = [vp, vp]
+    L.nm_ws_predict.argtypes = [vp, vp]
     L.nm_ws_residual_sample.argtypes = [vp, vp, C.c_int, vp, vp, C.POINTER(C.c_double), C.POINTER(C.c_double),
                                         C.POINTER(C.c_double)]
     L.nm_ws_train_residual.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_int, C.c_float,
@@ -426,6 +427,10 @@ def ws_attach(ctx: Context, net) -> None:
 
 def ws_features(ctx: Context, feat=None) -> None:
     ctx.check(load_library().nm_ws_features(ctx.handle, None if feat is None else feat.data_ptr()))
+
+
+def ws_predict(ctx: Context, x0) -> None:
+    ctx.check(load_library().nm_ws_predict(ctx.handle, x0.data_ptr()))
 
 
 def ws_target(ctx: Context, target) -> None:

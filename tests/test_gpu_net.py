@@ -347,3 +347,37 @@ def test_residual_training_lowers_the_initial_residual():
     print("residual training losses", [f"{x:.4g}" for x in losses[::5]], losses[-1], flush=True)
     assert losses[-1] < 0.5 * losses[0]
     net.close()
+
+
+def test_solver_inference_matches_the_full_network():
+    """The solver caches the material share of the first layer; its learned iterate must
+    agree with u~ + s net(f) evaluated on the full 31-channel features (BF16 activations:
+    a rounding can fall on the other side for a few entries), also after the weights change."""
+    import torch
+    pb = W.make_polycrystal(n=32, n_grains=6, seed=1006, n_steps=8)
+    N = pb.n_vox
+    net = nmb.Net(seed=9)
+    with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10, max_iter=500)) as ctx:
+        nmb.ws_attach(ctx, net)
+        for s in range(4):
+            nmb.newmark_step(ctx, pb.U(s + 1))
+        for trial in range(2):
+            st = nmb.get_state(ctx)
+            u, v, a = (st[k].reshape(3, N) for k in ("u", "v", "a"))
+            ut = u + pb.dt * v + pb.dt ** 2 * (0.5 - pb.beta) * a
+            sc = np.sqrt(np.mean((ut - u) ** 2))
+            x0 = torch.empty(3 * N, dtype=torch.float64, device="cuda")
+            nmb.ws_predict(ctx, x0)
+            f = torch.empty(N * 32, dtype=torch.int16, device="cuda")
+            nmb.ws_features(ctx, f)
+            pred = torch.empty(N * 4, dtype=torch.float32, device="cuda")
+            net.forward(pb.n, f, pred)
+            want = sc * pred.cpu().numpy().astype(np.float64).reshape(N, 4)[:, :3].T
+            got = x0.cpu().numpy().reshape(3, N) - ut
+            err = np.linalg.norm(got - want) / np.linalg.norm(want)
+            print(f"weights {trial}: cached-first-layer inference vs full network rel L2 {err:.2e}", flush=True)
+            assert err < 1e-2
+            # change the weights: the cached material share must be recomputed
+            w = net.get_params()
+            net.set_params(w * 1.05)
+    net.close()
