@@ -180,18 +180,23 @@ XInvArgs xi_args(nm_ctx* c, void* spec, void* out, const void* aux, const void* 
 // q = A p as seven passes: x-forward (3), D_y (3 -> 3), strain (6), x-inverse +
 // sigma = C : eps + x-forward (6), y part of the divergence, z part of the
 // divergence, x-inverse + rho p.  S and S2 are the two half-spectrum buffers.
+// The layout in fa carries the loop's stop flag (null outside a batched Krylov loop);
+// every pass of the chain gets it.
 template <typename T> int chain_operator(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
 {
     hipStream_t s = c->stream;
     void* spec = Prec<T>::spec(c);
     void* spec2 = Prec<T>::spec2(c);
     const void* tw = Prec<T>::tw(c);
+    const SpecLayout& lay = fa.lay;
+    SpecParams sp = c->sp;
+    sp.stop = lay.stop;
     LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
-    LCHK(c, launch_colop<T>(YOP_DERIV, c->sp, c->lay, spec, spec2, tw, s));
-    LCHK(c, launch_colop<T>(ZOP_STRAIN, c->sp, c->lay, spec, spec2, tw, s));
-    LCHK(c, launch_xstress<T>(c->n1, spec2, c->lay, c->phase, Prec<T>::C(c), tw, s));
-    LCHK(c, launch_colop<T>(YOP_DIV, c->sp, c->lay, spec, spec2, tw, s));
-    LCHK(c, launch_colop<T>(ZOP_DIVZ, c->sp, c->lay, spec, spec2, tw, s));
+    LCHK(c, launch_colop<T>(YOP_DERIV, sp, lay, spec, spec2, tw, s));
+    LCHK(c, launch_colop<T>(ZOP_STRAIN, sp, lay, spec, spec2, tw, s));
+    LCHK(c, launch_xstress<T>(c->n1, spec2, lay, c->phase, Prec<T>::C(c), tw, s));
+    LCHK(c, launch_colop<T>(YOP_DIV, sp, lay, spec, spec2, tw, s));
+    LCHK(c, launch_colop<T>(ZOP_DIVZ, sp, lay, spec, spec2, tw, s));
     LCHK(c, launch_xinv<T>(XI_OPERATOR, c->n1, ia, tw, s));
     return NM_OK;
 }
@@ -202,10 +207,13 @@ template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa
     hipStream_t s = c->stream;
     void* spec = Prec<T>::spec(c);
     const void* tw = Prec<T>::tw(c);
+    const SpecLayout& lay = fa.lay;
+    SpecParams sp = c->sp;
+    sp.stop = lay.stop;
     LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
-    LCHK(c, launch_ypass<T>(-1, 3, c->lay, spec, tw, s));
-    LCHK(c, launch_zprecond<T>(c->sp, c->lay, spec, tw, s));
-    LCHK(c, launch_ypass<T>(+1, 3, c->lay, spec, tw, s));
+    LCHK(c, launch_ypass<T>(-1, 3, lay, spec, tw, s));
+    LCHK(c, launch_zprecond<T>(sp, lay, spec, tw, s));
+    LCHK(c, launch_ypass<T>(+1, 3, lay, spec, tw, s));
     LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s));
     return NM_OK;
 }
@@ -271,7 +279,7 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
     if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite initial residual");
     if (bref <= 0) bref = 1.0;
     const double thr = tol * bref;
-    if ((fixed_iters < 0 && std::sqrt(rr) <= thr) || fixed_iters == 0) {
+    if ((fixed_iters < 0 && rr <= thr * thr) || fixed_iters == 0) {
         res->converged = true;
         return NM_OK;
     }
@@ -284,46 +292,74 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
         CHK(chain_precond<T>(c, XF_PLAIN, fa, ia));
         LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_RZ_INIT, 0, s));
     }
-    int it = 0;
+    // Iterations run in batches on the device: the residual reduction of each iteration
+    // counts it and raises the stop flag when the loop is done, after which every
+    // guarded kernel returns at once; the host reads the scalars once per batch and sizes
+    // the next batch from the observed convergence rate.
+    const double thr2 = thr * thr;
+    const bool fixed = fixed_iters >= 0;
+    LCHK(c, launch_loop_init(c->scal, thr2, fixed ? fixed_iters : max_iter, fixed ? 1 : 0, s));
+    const double* stop = c->scal + S_STOP;
+    int it = 0, batch = 1;
+    double rr_prev = rr;
+    int it_prev = 0;
     for (;;) {
-        // p = z + beta p ; q = P A p ; alpha = rz / p.q
-        {
-            XFwdArgs fa = xf_args(c, spec);
-            fa.src = z;
-            fa.p = p;
-            XInvArgs ia = xi_args(c, spec, q, p, Prec<T>::rho(c), mk, c->part_b);
-            CHK(chain_operator<T>(c, XF_PUPDATE, fa, ia));
-            LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_ALPHA, 0, s));
+        for (int k = 0; k < batch; k++) {
+            // p = z + beta p ; q = P A p ; alpha = rz / p.q
+            {
+                XFwdArgs fa = xf_args(c, spec);
+                fa.lay.stop = stop;
+                fa.src = z;
+                fa.p = p;
+                XInvArgs ia = xi_args(c, spec, q, p, Prec<T>::rho(c), mk, c->part_b);
+                ia.lay.stop = stop;
+                CHK(chain_operator<T>(c, XF_PUPDATE, fa, ia));
+                LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_ALPHA, 0, s, true));
+            }
+            // x += alpha p ; r -= alpha q ; z = P M r ; r.r (iteration count, stop test) ;
+            // beta = r.z_new / r.z_old
+            {
+                XFwdArgs fa = xf_args(c, spec);
+                fa.lay.stop = stop;
+                fa.x = x;
+                fa.r = r;
+                fa.p = p;
+                fa.q = q;
+                fa.partials = c->part_a;
+                XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
+                ia.lay.stop = stop;
+                CHK(chain_precond<T>(c, XF_UPDATE, fa, ia));
+                LCHK(c, launch_reduce(c->part_a, xfwd_blocks(c->n1, 3L * c->n2 * c->n3), c->scal, RED_RR_CHECK, 0,
+                                      s, true));
+                LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_BETA, 0, s, true));
+            }
         }
-        // x += alpha p ; r -= alpha q ; z = P M r ; beta = r.z_new / r.z_old
-        {
-            XFwdArgs fa = xf_args(c, spec);
-            fa.x = x;
-            fa.r = r;
-            fa.p = p;
-            fa.q = q;
-            fa.partials = c->part_a;
-            XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
-            CHK(chain_precond<T>(c, XF_UPDATE, fa, ia));
-            LCHK(c, launch_reduce(c->part_a, xfwd_blocks(c->n1, 3L * c->n2 * c->n3), c->scal, RED_STORE_RR, 0, s));
-            LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_BETA, 0, s));
-        }
-        it++;
         CHK(read_scalars(c));
+        it = (int)c->hscal[S_ITER];
         rr = c->hscal[S_RR];
         res->iters = it;
         res->rr = rr;
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual at iteration %d", it);
-        if (fixed_iters >= 0) {
-            if (it >= fixed_iters) break;
-        } else {
-            if (std::sqrt(rr) <= thr) break;
-            if (it >= max_iter) {
-                if (allow_unconverged) return NM_OK;
-                return fail(c, NM_ENOTCONV, "PCG did not reach tol %.3g in %d iterations (rel %.3g)", tol, max_iter,
-                            std::sqrt(rr) / bref);
-            }
+        if (c->hscal[S_STOP] != 0.0) {
+            if (fixed || rr <= thr2) break;
+            if (allow_unconverged) return NM_OK;
+            return fail(c, NM_ENOTCONV, "PCG did not reach tol %.3g in %d iterations (rel %.3g)", tol, max_iter,
+                        std::sqrt(rr) / bref);
         }
+        // next batch: the iterations the observed rate still needs (1 .. 6)
+        if (fixed) {
+            batch = fixed_iters - it;
+        } else {
+            double need = 1.0;
+            if (it > it_prev && rr > 0 && rr_prev > 0 && rr < rr_prev) {
+                const double rate = 0.5 * std::log(rr / rr_prev) / (it - it_prev); // log |r| per iteration
+                need = 0.5 * std::log(thr2 / rr) / rate;
+            }
+            batch = need < 1.0 ? 1 : (need > 6.0 ? 6 : (int)std::floor(need));
+        }
+        if (batch < 1) batch = 1;
+        rr_prev = rr;
+        it_prev = it;
     }
     res->converged = true;
     return NM_OK;

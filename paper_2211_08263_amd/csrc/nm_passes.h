@@ -16,6 +16,7 @@ struct SpecParams {
     double bdt2;      // beta dt^2
     double rhobar;    // volume-averaged density
     double Cbar[21];  // volume-averaged Voigt stiffness (upper triangle, row major)
+    const double* stop = nullptr; // device flag: when non-zero, kernels given this struct exit at once
 };
 
 // Layout of a half-spectrum buffer: element (c, kz, ky, kx) at
@@ -27,6 +28,7 @@ struct SpecLayout {
     int log2n2;
     long ps;        // kz (plane) stride, >= n2 * M
     long cs;        // component stride, >= n3 * ps
+    const double* stop = nullptr; // device flag: when non-zero, kernels given this layout exit at once
     __host__ __device__ __forceinline__ long line(long l) const
     {
         // x line l = (component, kz, ky) in row-major order
@@ -48,7 +50,13 @@ enum XInvMode { XI_PLAIN = 0, XI_OPERATOR = 1, XI_PRECOND = 2 };
 enum ColOp { YOP_DERIV = 0, YOP_DIV = 1, ZOP_STRAIN = 2, ZOP_DIVZ = 3 };
 
 // Device scalar block shared by the Krylov kernels (all double).
-enum ScalarSlot { S_ALPHA = 0, S_BETA = 1, S_FIRST = 2, S_RZ = 3, S_PQ = 4, S_RR = 5, S_COUNT = 8 };
+// S_STOP .. S_MODE drive a Krylov loop that runs several iterations between host checks:
+// the residual reduction counts iterations (S_ITER) and raises S_STOP once r.r <= S_THR2
+// (S_MODE 0) or the count reaches S_LIMIT; every guarded kernel after that returns at once.
+enum ScalarSlot {
+    S_ALPHA = 0, S_BETA = 1, S_FIRST = 2, S_RZ = 3, S_PQ = 4, S_RR = 5,
+    S_STOP = 8, S_ITER = 9, S_THR2 = 10, S_LIMIT = 11, S_MODE = 12, S_COUNT = 16
+};
 
 struct XFwdArgs {
     const void* src;      // XF_PLAIN: input field; XF_PUPDATE: z
@@ -90,6 +98,7 @@ int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* ph
 // In-place transform of ncomp components along y (dir -1 forward, +1 inverse).
 template <typename T>
 int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s);
+// (the y pass reads lay.stop)
 // Axis-wise derivative stages of the operator (ColOp); S and S2 are two 6-component spectra.
 template <typename T>
 int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, void* S2, const void* tw,

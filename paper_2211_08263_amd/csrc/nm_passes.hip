@@ -34,6 +34,9 @@
 
 namespace nm {
 
+// Early exit of a guarded kernel once the Krylov loop has stopped (uniform branch).
+__device__ __forceinline__ bool stopped(const double* stop) { return stop && *stop != 0.0; }
+
 // ---------------------------------------------------------------------------
 // Deterministic reductions (fixed shuffle tree per wave, fixed order across waves)
 // ---------------------------------------------------------------------------
@@ -100,6 +103,7 @@ template <int L, typename V> __device__ __forceinline__ void stage_twiddles(V* d
 template <typename T, int N1, int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __restrict__ tw)
 {
+    if (stopped(a.lay.stop)) return;
     using V = cx_t<T>;
     constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M;
     static_assert(G <= 64, "an x line must live inside one wavefront");
@@ -184,6 +188,7 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
 template <typename T, int N1, int R, int MODE>
 __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __restrict__ tw)
 {
+    if (stopped(a.lay.stop)) return;
     using V = cx_t<T>;
     constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M;
     static_assert(G <= 64, "an x line must live inside one wavefront");
@@ -276,6 +281,7 @@ template <typename T, int N1, int R>
 __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout lay, const uint16_t* __restrict__ phase,
                                                     const T* __restrict__ C21, const cx_t<T>* __restrict__ tw)
 {
+    if (stopped(lay.stop)) return;
     using V = cx_t<T>;
     constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M;
     static_assert(G <= 64, "an x line must live inside one wavefront");
@@ -386,8 +392,9 @@ template <int TXC> struct ColAddrT {
 
 template <typename T, int L, int R, int DIR, int BLK, int TXC>
 __global__ __launch_bounds__(BLK) void k_ypass(cx_t<T>* __restrict__ data, long colstride, long planestride, long cs,
-                                               int TXr, const cx_t<T>* __restrict__ tw)
+                                               int TXr, const cx_t<T>* __restrict__ tw, const double* stop)
 {
+    if (stopped(stop)) return;
     using V = cx_t<T>;
     constexpr int G = L / R;
     const int TX = TXC > 0 ? TXC : TXr;
@@ -421,6 +428,7 @@ template <typename T, int L, int R, int BLK, int TXC>
 __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, long NS, long colstride, int TXr,
                                                   SpecParams sp, const cx_t<T>* __restrict__ tw)
 {
+    if (stopped(sp.stop)) return;
     using V = cx_t<T>;
     constexpr int G = L / R;
     const int TX = TXC > 0 ? TXC : TXr;
@@ -440,13 +448,15 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
 #pragma unroll
     for (int m = 0; m < R; m++) xi3[m] = (T)(sp.k3 * freq_index(t + m * G, sp.n3));
 
+    // all three components' loads go out before the first transform (the barriers of
+    // the LDS exchanges would otherwise hold each load back behind the previous transform)
     V u[3][R];
 #pragma unroll
-    for (int j = 0; j < 3; j++) {
+    for (int j = 0; j < 3; j++)
 #pragma unroll
         for (int m = 0; m < R; m++) u[j][m] = col[j * NS + (long)(t + m * G) * colstride];
-        group_fft<L, R, -1>(u[j], t, lds, addr, twL);
-    }
+#pragma unroll
+    for (int j = 0; j < 3; j++) group_fft<L, R, -1>(u[j], t, lds, addr, twL);
     T C[6][6];
     {
         int o = 0;
@@ -526,6 +536,7 @@ template <typename T, int L, int R, int OP, int BLK, int TXC>
 __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>* __restrict__ S2, long rowstride,
                                                long cs, int TXr, SpecParams sp, const cx_t<T>* __restrict__ tw)
 {
+    if (stopped(sp.stop)) return;
     using V = cx_t<T>;
     constexpr int G = L / R;
     constexpr bool YAX = (OP == YOP_DERIV || OP == YOP_DIV);
@@ -776,14 +787,14 @@ int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const vo
         cx_t<T>* d = (cx_t<T>*)spec;
         if (M >= TXP) {
             if (dir < 0)
-                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
             else
-                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
         } else {
             if (dir < 0)
-                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
             else
-                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
         }
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;

@@ -5,10 +5,16 @@
 
 namespace nm {
 
-enum ReduceAction { RED_STORE_RR = 0, RED_ALPHA = 1, RED_RZ_INIT = 2, RED_BETA = 3, RED_STORE_SLOT = 4 };
+enum ReduceAction { RED_STORE_RR = 0, RED_ALPHA = 1, RED_RZ_INIT = 2, RED_BETA = 3, RED_STORE_SLOT = 4, RED_RR_CHECK = 5 };
 
 // Deterministic sum of n per-block partials into the scalar block, then the action.
-int launch_reduce(const double* partials, int n, double* scal, int action, int slot, hipStream_t s);
+// Arm a batched Krylov loop: clear S_STOP and S_ITER, set S_THR2, S_LIMIT, S_MODE (1: run
+// exactly `limit` iterations).
+int launch_loop_init(double* scal, double thr2, int limit, int fixed, hipStream_t s);
+// guarded: the kernel does nothing once scal[S_STOP] is set.  RED_RR_CHECK stores r.r,
+// counts the iteration and sets S_STOP when the loop is done (see ScalarSlot).
+int launch_reduce(const double* partials, int n, double* scal, int action, int slot, hipStream_t s,
+                  bool guarded = false);
 
 // Number of partials written by the grid-stride kernels below.
 int vec_blocks(long n);

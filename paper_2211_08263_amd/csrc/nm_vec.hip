@@ -35,14 +35,24 @@ __device__ __forceinline__ double block_sum_v(double v)
 
 // One block of 1024 threads: thread i sums partials i, i+1024, ... in order.
 __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part, int n, double* scal, int action,
-                                                 int slot)
+                                                 int slot, int guarded)
 {
+    if (guarded && scal[S_STOP] != 0.0) return;
     double v = 0.0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) v += part[i];
     const double s = block_sum_v(v);
     if (threadIdx.x == 0) {
         switch (action) {
         case RED_STORE_RR: scal[S_RR] = s; break;
+        case RED_RR_CHECK: {
+            scal[S_RR] = s;
+            const double it = scal[S_ITER] + 1.0;
+            scal[S_ITER] = it;
+            const bool done = scal[S_MODE] != 0.0 ? it >= scal[S_LIMIT]
+                                                  : (s <= scal[S_THR2] || it >= scal[S_LIMIT] || !(s < 1e300));
+            if (done) scal[S_STOP] = 1.0;
+            break;
+        }
         case RED_ALPHA:
             scal[S_PQ] = s;
             scal[S_ALPHA] = scal[S_RZ] / s;
@@ -61,9 +71,25 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
     }
 }
 
-int launch_reduce(const double* partials, int n, double* scal, int action, int slot, hipStream_t s)
+__global__ void k_loop_init(double* scal, double thr2, double limit, double mode)
 {
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partials, n, scal, action, slot);
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        scal[S_STOP] = 0.0;
+        scal[S_ITER] = 0.0;
+        scal[S_THR2] = thr2;
+        scal[S_LIMIT] = limit;
+        scal[S_MODE] = mode;
+    }
+}
+int launch_loop_init(double* scal, double thr2, int limit, int fixed, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_loop_init, dim3(1), dim3(64), 0, s, scal, thr2, (double)limit, (double)fixed);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+int launch_reduce(const double* partials, int n, double* scal, int action, int slot, hipStream_t s, bool guarded)
+{
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(1024), 0, s, partials, n, scal, action, slot, guarded ? 1 : 0);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
