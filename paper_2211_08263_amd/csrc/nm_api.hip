@@ -311,19 +311,18 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
                 fa.lay.stop = stop;
                 fa.src = z;
                 fa.p = p;
+                fa.x = x;
                 XInvArgs ia = xi_args(c, spec, q, p, Prec<T>::rho(c), mk, c->part_b);
                 ia.lay.stop = stop;
                 CHK(chain_operator<T>(c, XF_PUPDATE, fa, ia));
                 LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_ALPHA, 0, s, true));
             }
-            // x += alpha p ; r -= alpha q ; z = P M r ; r.r (iteration count, stop test) ;
-            // beta = r.z_new / r.z_old
+            // r -= alpha q ; z = P M r ; r.r (iteration count, stop test) ;
+            // beta = r.z_new / r.z_old   (x += alpha p follows in the next p update)
             {
                 XFwdArgs fa = xf_args(c, spec);
                 fa.lay.stop = stop;
-                fa.x = x;
                 fa.r = r;
-                fa.p = p;
                 fa.q = q;
                 fa.partials = c->part_a;
                 XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
@@ -341,6 +340,8 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
         res->rr = rr;
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual at iteration %d", it);
         if (c->hscal[S_STOP] != 0.0) {
+            // the last iteration's x += alpha p
+            LCHK(c, launch_axpy_scal<T>(x, p, c->scal + S_ALPHA, n, s));
             if (fixed || rr <= thr2) break;
             if (allow_unconverged) return NM_OK;
             return fail(c, NM_ENOTCONV, "PCG did not reach tol %.3g in %d iterations (rel %.3g)", tol, max_iter,

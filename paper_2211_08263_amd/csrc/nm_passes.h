@@ -38,6 +38,7 @@ struct SpecLayout {
 };
 
 // Fused stage in front of the x-direction real-to-complex transform.
+// XF_PUPDATE: p = z + beta p (and the deferred x += alpha p_old); XF_UPDATE: r -= alpha q.
 enum XFwdMode { XF_PLAIN = 0, XF_PUPDATE = 1, XF_UPDATE = 2 };
 // Fused stage after the x-direction complex-to-real transform.
 enum XInvMode { XI_PLAIN = 0, XI_OPERATOR = 1, XI_PRECOND = 2 };
@@ -60,8 +61,8 @@ enum ScalarSlot {
 
 struct XFwdArgs {
     const void* src;      // XF_PLAIN: input field; XF_PUPDATE: z
-    void* p;              // XF_PUPDATE: p (in/out); XF_UPDATE: p (in)
-    void* x;              // XF_UPDATE: x (in/out)
+    void* p;              // XF_PUPDATE: p (in/out)
+    void* x;              // XF_PUPDATE: x (in/out; x += alpha p_old after the first iteration)
     void* r;              // XF_UPDATE: r (in/out)
     const void* q;        // XF_UPDATE: q (in)
     const double* scal;   // device scalars

@@ -128,9 +128,13 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
 #pragma unroll
             for (int m = 0; m < R; m++) v[m] = src[t + m * G];
         } else if constexpr (MODE == XF_PUPDATE) {
+            // p = z + beta p, and the previous iteration's x += alpha p (deferred to here,
+            // where the old p is read anyway; the caller applies the last one)
             const V* z = (const V*)a.src + off;
             V* p = (V*)a.p + off;
+            V* x = (V*)a.x + off;
             const T beta = (T)a.scal[S_BETA];
+            const T alpha = (T)a.scal[S_ALPHA];
             const bool first = a.scal[S_FIRST] != 0.0;
 #pragma unroll
             for (int m = 0; m < R; m++) {
@@ -138,25 +142,25 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
                 V zz = z[i];
                 V pp = zz;
                 if (!first) {
-                    V po = p[i];
+                    const V po = p[i];
+                    V xx = x[i];
+                    xx = V{xx.x + alpha * po.x, xx.y + alpha * po.y};
+                    x[i] = xx;
                     pp = V{zz.x + beta * po.x, zz.y + beta * po.y};
                 }
                 p[i] = pp;
                 v[m] = pp;
             }
         } else {
+            // r -= alpha q and the partial sums of r.r
             const T alpha = (T)a.scal[S_ALPHA];
-            V* x = (V*)a.x + off;
             V* r = (V*)a.r + off;
-            const V* p = (const V*)a.p + off;
             const V* q = (const V*)a.q + off;
 #pragma unroll
             for (int m = 0; m < R; m++) {
                 const int i = t + m * G;
-                V pp = p[i], qq = q[i], xx = x[i], rr = r[i];
-                xx = V{xx.x + alpha * pp.x, xx.y + alpha * pp.y};
+                V qq = q[i], rr = r[i];
                 rr = V{rr.x - alpha * qq.x, rr.y - alpha * qq.y};
-                x[i] = xx;
                 r[i] = rr;
                 part += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
                 v[m] = rr;

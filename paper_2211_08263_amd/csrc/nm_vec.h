@@ -8,6 +8,8 @@ namespace nm {
 enum ReduceAction { RED_STORE_RR = 0, RED_ALPHA = 1, RED_RZ_INIT = 2, RED_BETA = 3, RED_STORE_SLOT = 4, RED_RR_CHECK = 5 };
 
 // Deterministic sum of n per-block partials into the scalar block, then the action.
+// x += alpha p, alpha read from the device (the deferred last update of a Krylov loop).
+template <typename T> int launch_axpy_scal(T* x, const T* p, const double* alpha, long n, hipStream_t s);
 // Arm a batched Krylov loop: clear S_STOP and S_ITER, set S_THR2, S_LIMIT, S_MODE (1: run
 // exactly `limit` iterations).
 int launch_loop_init(double* scal, double thr2, int limit, int fixed, hipStream_t s);

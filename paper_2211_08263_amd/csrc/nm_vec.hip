@@ -71,6 +71,23 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
     }
 }
 
+// x += alpha p with alpha read from the device
+template <typename T>
+__global__ __launch_bounds__(kBlock) void k_axpy_scal(T* __restrict__ x, const T* __restrict__ p,
+                                                      const double* __restrict__ alpha, long n)
+{
+    const T a = (T)alpha[0];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = x[i] + a * p[i];
+}
+template <typename T> int launch_axpy_scal(T* x, const T* p, const double* alpha, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_axpy_scal<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, p, alpha, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+template int launch_axpy_scal<double>(double*, const double*, const double*, long, hipStream_t);
+template int launch_axpy_scal<float>(float*, const float*, const double*, long, hipStream_t);
+
 __global__ void k_loop_init(double* scal, double thr2, double limit, double mode)
 {
     if (threadIdx.x == 0 && blockIdx.x == 0) {
