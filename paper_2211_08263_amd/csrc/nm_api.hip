@@ -210,11 +210,18 @@ template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa
     const SpecLayout& lay = fa.lay;
     SpecParams sp = c->sp;
     sp.stop = lay.stop;
+    // with ia.partials the product r . z is summed on the spectrum inside the z pass, so
+    // the final x pass need not read r again
+    XInvArgs ib = ia;
+    if (ia.partials) {
+        ib.partials = nullptr;
+        ib.aux = nullptr;
+    }
     LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
     LCHK(c, launch_ypass<T>(-1, 3, lay, spec, tw, s));
-    LCHK(c, launch_zprecond<T>(sp, lay, spec, tw, s));
+    LCHK(c, launch_zprecond<T>(sp, lay, spec, tw, s, ia.partials));
     LCHK(c, launch_ypass<T>(+1, 3, lay, spec, tw, s));
-    LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ia, tw, s));
+    LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ib, tw, s));
     return NM_OK;
 }
 
@@ -284,13 +291,14 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
         return NM_OK;
     }
     const int nb = xinv_blocks(c->n1, 3L * c->n2 * c->n3);
+    const int nbz = zprecond_blocks<T>(c->sp);
     // z = P M r, rz = r.z
     {
         XFwdArgs fa = xf_args(c, spec);
         fa.src = r;
         XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
         CHK(chain_precond<T>(c, XF_PLAIN, fa, ia));
-        LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_RZ_INIT, 0, s));
+        LCHK(c, launch_reduce(c->part_b, nbz, c->scal, RED_RZ_INIT, 0, s));
     }
     // Iterations run in batches on the device: the residual reduction of each iteration
     // counts it and raises the stop flag when the loop is done, after which every
@@ -330,7 +338,7 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
                 CHK(chain_precond<T>(c, XF_UPDATE, fa, ia));
                 LCHK(c, launch_reduce(c->part_a, xfwd_blocks(c->n1, 3L * c->n2 * c->n3), c->scal, RED_RR_CHECK, 0,
                                       s, true));
-                LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_BETA, 0, s, true));
+                LCHK(c, launch_reduce(c->part_b, nbz, c->scal, RED_BETA, 0, s, true));
             }
         }
         CHK(read_scalars(c));
@@ -831,7 +839,8 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     CHK(dalloc(c, &c->scal, S_COUNT));
     HIPCHK(c, hipMemset(c->scal, 0, S_COUNT * sizeof(double)));
     HIPCHK(c, hipHostMalloc((void**)&c->hscal, S_COUNT * sizeof(double), hipHostMallocDefault));
-    c->npart = std::max(xfwd_blocks(c->n1, 3L * c->n2 * c->n3), vec_blocks(n));
+    c->npart = std::max({xfwd_blocks(c->n1, 3L * c->n2 * c->n3), vec_blocks(n), zprecond_blocks<double>(c->sp),
+                         zprecond_blocks<float>(c->sp)});
     CHK(dalloc(c, &c->part_a, c->npart));
     CHK(dalloc(c, &c->part_b, c->npart));
     // fields

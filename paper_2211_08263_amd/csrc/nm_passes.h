@@ -105,7 +105,11 @@ template <typename T>
 int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, void* S2, const void* tw,
                  hipStream_t s);
 // Preconditioner z pass in place: z-forward, (beta dt^2 K + rhobar I)^-1, z-inverse.
+// partials (or null): per-block sums of r . z taken on the spectrum (Parseval), one per
+// block of zprecond_blocks<T>(sp).
 template <typename T>
-int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s);
+int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s,
+                    double* partials = nullptr);
+template <typename T> int zprecond_blocks(const SpecParams& sp);
 
 } // namespace nm

@@ -221,7 +221,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int n = t + m * G;
-            au[m] = valid ? aux[n] : V{0, 0};
+            au[m] = (valid && a.aux) ? aux[n] : V{0, 0};
             ph[m] = (valid && MODE == XI_OPERATOR) ? ((const uint32_t*)a.phase)[vline * M + n] : 0u;
             mk[m] = (valid && a.mask) ? ((const uint16_t*)a.mask)[vline * M + n] : (uint16_t)0;
         }
@@ -430,7 +430,8 @@ template <typename T> struct ZOps {
 // at one ky; data in place.
 template <typename T, int L, int R, int BLK, int TXC>
 __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, long NS, long colstride, int TXr,
-                                                  SpecParams sp, const cx_t<T>* __restrict__ tw)
+                                                  SpecParams sp, const cx_t<T>* __restrict__ tw,
+                                                  double* __restrict__ partials)
 {
     if (stopped(sp.stop)) return;
     using V = cx_t<T>;
@@ -474,6 +475,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
             }
     }
     const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
+    double part = 0.0;
 #pragma unroll
     for (int m = 0; m < R; m++) {
         const T x1 = xi1, x2 = xi2, x3 = xi3[m];
@@ -518,9 +520,26 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
             z1 = cscale(cadd(cadd(cscale(r0, c01), cscale(r1, c11)), cscale(r2, c12)), id);
             z2 = cscale(cadd(cadd(cscale(r0, c02), cscale(r1, c12)), cscale(r2, c22)), id);
         }
+        // r . z by Parseval on the half spectrum: bins 0 < kx < n1/2 stand for themselves
+        // and their mirrors (weight 2); the packed slot kx = 0 holds the kx = 0 and
+        // kx = n1/2 planes, whose cross terms are imaginary (weight 1, real part)
+        part += (kx == 0 ? 1.0 : 2.0) *
+                ((double)u[0][m].x * z0.x + (double)u[0][m].y * z0.y + (double)u[1][m].x * z1.x +
+                 (double)u[1][m].y * z1.y + (double)u[2][m].x * z2.x + (double)u[2][m].y * z2.y);
         u[0][m] = z0;
         u[1][m] = z1;
         u[2][m] = z2;
+    }
+    if (partials) {
+        __shared__ double red[BLK / 64 > 0 ? BLK / 64 : 1];
+        part = wave_sum(part);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double tot = 0.0;
+            for (int w = 0; w < (int)((blockDim.x + 63) / 64); w++) tot += red[w];
+            partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        }
     }
 #pragma unroll
     for (int j = 0; j < 3; j++) {
@@ -806,14 +825,36 @@ int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const vo
 
 template <typename T, int L, int BLK, int TXC>
 static void zprecond_dispatch(dim3 grid, dim3 block, hipStream_t s, cx_t<T>* spec, const SpecLayout& lay, int TX,
-                              const SpecParams& sp, const cx_t<T>* t)
+                              const SpecParams& sp, const cx_t<T>* t, double* partials)
 {
     constexpr int R = zspec_radix<T, L>();
-    hipLaunchKernelGGL((k_zprecond<T, L, R, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX, sp, t);
+    hipLaunchKernelGGL((k_zprecond<T, L, R, BLK, TXC>), grid, block, 0, s, spec, lay.cs, lay.ps, TX, sp, t,
+                       partials);
+}
+
+template <typename T> int zprecond_blocks(const SpecParams& sp)
+{
+    const int M = sp.n1 / 2;
+    constexpr int BLK = zspec_block<T>();
+    if (sp.n3 == 1) {
+        const int TX = M < BLK ? M : BLK;
+        return (M / TX) * sp.n2;
+    }
+    int nb = 0;
+    [&]() -> int {
+        NM_SIZE_SWITCH(sp.n3, {
+            constexpr int G = NN / zspec_radix<T, NN>();
+            constexpr int TXP = BLK / G;
+            nb = (M >= TXP ? M / TXP : 1) * sp.n2;
+        })
+        return 0;
+    }();
+    return nb;
 }
 
 template <typename T>
-int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s)
+int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, const void* tw, hipStream_t s,
+                    double* partials)
 {
     const int M = sp.n1 / 2;
     const cx_t<T>* t = (const cx_t<T>*)tw;
@@ -821,15 +862,16 @@ int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, con
     constexpr int BLK = zspec_block<T>();
     if (sp.n3 == 1) {
         const int TX = M < BLK ? M : BLK;
-        zprecond_dispatch<T, 1, BLK, 0>(dim3(M / TX, sp.n2), dim3(TX), s, d, lay, TX, sp, t);
+        zprecond_dispatch<T, 1, BLK, 0>(dim3(M / TX, sp.n2), dim3(TX), s, d, lay, TX, sp, t, partials);
     } else {
         NM_SIZE_SWITCH(sp.n3, {
             constexpr int G = NN / zspec_radix<T, NN>();
             constexpr int TXP = BLK / G;
             if (M >= TXP)
-                zprecond_dispatch<T, NN, BLK, TXP>(dim3(M / TXP, sp.n2), dim3(TXP * G), s, d, lay, TXP, sp, t);
+                zprecond_dispatch<T, NN, BLK, TXP>(dim3(M / TXP, sp.n2), dim3(TXP * G), s, d, lay, TXP, sp, t,
+                                                    partials);
             else
-                zprecond_dispatch<T, NN, BLK, 0>(dim3(1, sp.n2), dim3(M * G), s, d, lay, M, sp, t);
+                zprecond_dispatch<T, NN, BLK, 0>(dim3(1, sp.n2), dim3(M * G), s, d, lay, M, sp, t, partials);
         })
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -901,7 +943,8 @@ int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, v
     template int launch_xstress<T>(int, void*, const SpecLayout&, const uint16_t*, const void*, const void*,          \
                                    hipStream_t);                                                                       \
     template int launch_ypass<T>(int, int, const SpecLayout&, void*, const void*, hipStream_t);                        \
-    template int launch_zprecond<T>(const SpecParams&, const SpecLayout&, void*, const void*, hipStream_t);          \
+    template int launch_zprecond<T>(const SpecParams&, const SpecLayout&, void*, const void*, hipStream_t, double*); \
+    template int zprecond_blocks<T>(const SpecParams&);                                                             \
     template int launch_colop<T>(int, const SpecParams&, const SpecLayout&, void*, void*, const void*, hipStream_t);
 NM_INST(double)
 NM_INST(float)
