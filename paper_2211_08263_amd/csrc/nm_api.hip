@@ -26,7 +26,7 @@ using namespace nm;
 #define NM_PAD_PLANE 0
 #endif
 #ifndef NM_PAD_COMP
-#define NM_PAD_COMP 0
+#define NM_PAD_COMP 1040
 #endif
 
 struct nm_ctx {
@@ -177,21 +177,16 @@ XInvArgs xi_args(nm_ctx* c, void* spec, void* out, const void* aux, const void* 
     return a;
 }
 
-// q = A p as seven passes: x-forward (3), D_y (3 -> 3), strain (6), x-inverse +
-// sigma = C : eps + x-forward (6), y part of the divergence, z part of the
-// divergence, x-inverse + rho p.  S and S2 are the two half-spectrum buffers.
-// The layout in fa carries the loop's stop flag (null outside a batched Krylov loop);
-// every pass of the chain gets it.
-template <typename T> int chain_operator(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
+// The six passes of q = A p after the x-forward one (which left the x spectrum of p in S).
+template <typename T> int chain_operator_rest(nm_ctx* c, const XInvArgs& ia)
 {
     hipStream_t s = c->stream;
     void* spec = Prec<T>::spec(c);
     void* spec2 = Prec<T>::spec2(c);
     const void* tw = Prec<T>::tw(c);
-    const SpecLayout& lay = fa.lay;
+    const SpecLayout& lay = ia.lay;
     SpecParams sp = c->sp;
     sp.stop = lay.stop;
-    LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
     LCHK(c, launch_colop<T>(YOP_DERIV, sp, lay, spec, spec2, tw, s));
     LCHK(c, launch_colop<T>(ZOP_STRAIN, sp, lay, spec, spec2, tw, s));
     LCHK(c, launch_xstress<T>(c->n1, spec2, lay, c->phase, Prec<T>::C(c), tw, s));
@@ -201,8 +196,21 @@ template <typename T> int chain_operator(nm_ctx* c, int fmode, const XFwdArgs& f
     return NM_OK;
 }
 
-// z = M r: x/y/z forward, pointwise (beta dt^2 K + rhobar I)^-1, inverse.
-template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
+// q = A p as seven passes: x-forward (3), D_y (3 -> 3), strain (6), x-inverse +
+// sigma = C : eps + x-forward (6), y part of the divergence, z part of the
+// divergence, x-inverse + rho p.  S and S2 are the two half-spectrum buffers.
+// The layout in fa carries the loop's stop flag (null outside a batched Krylov loop);
+// every pass of the chain gets it.
+template <typename T> int chain_operator(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
+{
+    LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, Prec<T>::tw(c), c->stream));
+    return chain_operator_rest<T>(c, ia);
+}
+
+// z = M r up to the x-inverse: x/y/z forward, pointwise (beta dt^2 K + rhobar I)^-1,
+// z and y inverse; the x spectrum of z is left in S.  partials (or null): per-block
+// sums of r . z taken on the spectrum inside the z pass.
+template <typename T> int chain_precond_spec(nm_ctx* c, int fmode, const XFwdArgs& fa, double* partials)
 {
     hipStream_t s = c->stream;
     void* spec = Prec<T>::spec(c);
@@ -210,6 +218,16 @@ template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa
     const SpecLayout& lay = fa.lay;
     SpecParams sp = c->sp;
     sp.stop = lay.stop;
+    LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
+    LCHK(c, launch_ypass<T>(-1, 3, lay, spec, tw, s));
+    LCHK(c, launch_zprecond<T>(sp, lay, spec, tw, s, partials));
+    LCHK(c, launch_ypass<T>(+1, 3, lay, spec, tw, s));
+    return NM_OK;
+}
+
+// z = M r: x/y/z forward, pointwise (beta dt^2 K + rhobar I)^-1, inverse.
+template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa, const XInvArgs& ia)
+{
     // with ia.partials the product r . z is summed on the spectrum inside the z pass, so
     // the final x pass need not read r again
     XInvArgs ib = ia;
@@ -217,11 +235,8 @@ template <typename T> int chain_precond(nm_ctx* c, int fmode, const XFwdArgs& fa
         ib.partials = nullptr;
         ib.aux = nullptr;
     }
-    LCHK(c, launch_xfwd<T>(fmode, c->n1, fa, tw, s));
-    LCHK(c, launch_ypass<T>(-1, 3, lay, spec, tw, s));
-    LCHK(c, launch_zprecond<T>(sp, lay, spec, tw, s, ia.partials));
-    LCHK(c, launch_ypass<T>(+1, 3, lay, spec, tw, s));
-    LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ib, tw, s));
+    CHK(chain_precond_spec<T>(c, fmode, fa, ia.partials));
+    LCHK(c, launch_xinv<T>(XI_PRECOND, c->n1, ib, Prec<T>::tw(c), c->stream));
     return NM_OK;
 }
 
@@ -292,12 +307,11 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
     }
     const int nb = xinv_blocks(c->n1, 3L * c->n2 * c->n3);
     const int nbz = zprecond_blocks<T>(c->sp);
-    // z = P M r, rz = r.z
+    // z = P M r as its x spectrum (the x-inverse is fused into the first p update), rz = r.z
     {
         XFwdArgs fa = xf_args(c, spec);
         fa.src = r;
-        XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
-        CHK(chain_precond<T>(c, XF_PLAIN, fa, ia));
+        CHK(chain_precond_spec<T>(c, XF_PLAIN, fa, c->part_b));
         LCHK(c, launch_reduce(c->part_b, nbz, c->scal, RED_RZ_INIT, 0, s));
     }
     // Iterations run in batches on the device: the residual reduction of each iteration
@@ -313,31 +327,36 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
     int it_prev = 0;
     for (;;) {
         for (int k = 0; k < batch; k++) {
-            // p = z + beta p ; q = P A p ; alpha = rz / p.q
+            // z = P x-inv(Z); p = z + beta p (x += alpha p_old) with its x spectrum;
+            // q = P A p ; alpha = rz / p.q
             {
-                XFwdArgs fa = xf_args(c, spec);
-                fa.lay.stop = stop;
-                fa.src = z;
-                fa.p = p;
-                fa.x = x;
+                XInvArgs pa = xi_args(c, spec, nullptr, nullptr, nullptr, mk, nullptr);
+                pa.lay.stop = stop;
+                pa.p = p;
+                pa.x = x;
+                pa.scal = c->scal;
+                LCHK(c, launch_xpupdate<T>(c->n1, pa, Prec<T>::tw(c), s));
                 XInvArgs ia = xi_args(c, spec, q, p, Prec<T>::rho(c), mk, c->part_b);
                 ia.lay.stop = stop;
-                CHK(chain_operator<T>(c, XF_PUPDATE, fa, ia));
+                CHK(chain_operator_rest<T>(c, ia));
                 LCHK(c, launch_reduce(c->part_b, nb, c->scal, RED_ALPHA, 0, s, true));
             }
-            // r -= alpha q ; z = P M r ; r.r (iteration count, stop test) ;
-            // beta = r.z_new / r.z_old   (x += alpha p follows in the next p update)
+            // r -= alpha q ; r.r (iteration count, stop test) ; Z = M r with r.z on the
+            // spectrum ; beta = r.z_new / r.z_old   (x += alpha p follows in the next p update)
             {
                 XFwdArgs fa = xf_args(c, spec);
                 fa.lay.stop = stop;
                 fa.r = r;
                 fa.q = q;
                 fa.partials = c->part_a;
-                XInvArgs ia = xi_args(c, spec, z, r, Prec<T>::rho(c), mk, c->part_b);
-                ia.lay.stop = stop;
-                CHK(chain_precond<T>(c, XF_UPDATE, fa, ia));
+                LCHK(c, launch_xfwd<T>(XF_UPDATE, c->n1, fa, Prec<T>::tw(c), s));
                 LCHK(c, launch_reduce(c->part_a, xfwd_blocks(c->n1, 3L * c->n2 * c->n3), c->scal, RED_RR_CHECK, 0,
                                       s, true));
+                SpecParams sp = c->sp;
+                sp.stop = stop;
+                LCHK(c, launch_ypass<T>(-1, 3, fa.lay, spec, Prec<T>::tw(c), s));
+                LCHK(c, launch_zprecond<T>(sp, fa.lay, spec, Prec<T>::tw(c), s, c->part_b));
+                LCHK(c, launch_ypass<T>(+1, 3, fa.lay, spec, Prec<T>::tw(c), s));
                 LCHK(c, launch_reduce(c->part_b, nbz, c->scal, RED_BETA, 0, s, true));
             }
         }

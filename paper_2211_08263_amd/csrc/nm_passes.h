@@ -84,6 +84,9 @@ struct XInvArgs {
     long nlines;
     long lines_per_comp;  // n2 * n3
     int dim;
+    void* p = nullptr;            // launch_xpupdate: search direction (in/out)
+    void* x = nullptr;            // launch_xpupdate: iterate (in/out)
+    const double* scal = nullptr; // launch_xpupdate: device scalars (alpha, beta, first)
 };
 
 // Number of blocks a launch uses (sizes the partials array).
@@ -92,6 +95,9 @@ int xinv_blocks(int n1, long nlines);
 
 template <typename T> int launch_xfwd(int mode, int n1, const XFwdArgs& a, const void* tw, hipStream_t s);
 template <typename T> int launch_xinv(int mode, int n1, const XInvArgs& a, const void* tw, hipStream_t s);
+// In place on the half spectrum a.spec: z = mask(x-inverse), p = z + beta p with the
+// deferred x += alpha p_old (p = z while scal[S_FIRST] is set), spectrum <- x-forward(p).
+template <typename T> int launch_xpupdate(int n1, const XInvArgs& a, const void* tw, hipStream_t s);
 // In-place x-inverse, Voigt stress sigma = C_g : eps, x-forward on 6 components.
 template <typename T>
 int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* phase, const void* C21, const void* tw,

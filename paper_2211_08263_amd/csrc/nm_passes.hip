@@ -28,6 +28,10 @@
 #ifndef NM_STRESS_PF64
 #define NM_STRESS_PF64 2
 #endif
+// Column passes address their tiles as a uniform base plus 32-bit lane offsets.
+#ifndef NM_COL_OFF32
+#define NM_COL_OFF32 1
+#endif
 #ifndef NM_STRESS_PF32
 #define NM_STRESS_PF32 6
 #endif
@@ -269,6 +273,99 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
     }
 }
 
+// Last pass of the preconditioner fused with the first pass of the next operator apply
+// (in place on the half spectrum): z = P x-inv(Z) (the preconditioned residual, masked
+// on Gamma), p = z + beta p and the deferred x += alpha p_old (p = z on the first
+// iteration), then the x-forward transform of the new p overwrites the line.  The
+// preconditioned residual never goes to memory.
+template <typename T, int N1, int R>
+__global__ __launch_bounds__(kBlock) void k_xpupdate(XInvArgs a, const cx_t<T>* __restrict__ tw)
+{
+    if (stopped(a.lay.stop)) return;
+    using V = cx_t<T>;
+    constexpr int M = N1 / 2, G = M / R, LPB = kBlock / G, LP = M;
+    static_assert(G <= 64, "an x line must live inside one wavefront");
+    __shared__ V lds[LPB * LP];
+    __shared__ V twsm[M + N1];
+    stage_twiddles<M>(twsm, tw);
+    stage_twiddles<N1>(twsm + M, tw);
+    __syncthreads();
+    const V* twM = twsm;
+    const V* twN = twsm + M;
+    const int tid = threadIdx.x, ll = tid / G, t = tid % G;
+    const long line = (long)blockIdx.x * LPB + ll;
+    const bool valid = line < a.nlines;
+    const long off = line * M;
+    const long soff = a.lay.line(line);
+    V* spec = (V*)a.spec;
+    V v[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) v[m] = valid ? spec[soff + t + m * G] : V{0, 0};
+    // the real-space operands are fetched before the transforms
+    const bool first = a.scal[S_FIRST] != 0.0;
+    const T beta = (T)a.scal[S_BETA];
+    const T alpha = (T)a.scal[S_ALPHA];
+    V* p = (V*)a.p + off;
+    V* x = (V*)a.x + off;
+    V po[R], xo[R];
+    uint16_t mk[R];
+    const long vline = line % a.lines_per_comp;
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int n = t + m * G;
+        po[m] = (valid && !first) ? p[n] : V{0, 0};
+        xo[m] = (valid && !first) ? x[n] : V{0, 0};
+        mk[m] = (valid && a.mask) ? ((const uint16_t*)a.mask)[vline * M + n] : (uint16_t)0;
+    }
+    LineAddr<R, (int)sizeof(V)> addr{ll * LP};
+#pragma unroll
+    for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
+    group_sync<true>();
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        const int k = t + m * G;
+        V xm = lds[addr((M - k) & (M - 1))];
+        v[m] = c2r_pre(k, v[m], xm, twN[k]);
+    }
+    group_sync<true>();
+    group_fft<M, R, +1, true>(v, t, lds, addr, twM);
+    const bool zero_comp = (a.dim == 2) && (line / a.lines_per_comp == 2);
+#pragma unroll
+    for (int m = 0; m < R; m++) {
+        V z = v[m];
+        if (mk[m] & 0x00ffu) z.x = 0;
+        if (mk[m] & 0xff00u) z.y = 0;
+        if (zero_comp) z = V{0, 0};
+        if (!first) {
+            xo[m] = V{xo[m].x + alpha * po[m].x, xo[m].y + alpha * po[m].y};
+            z = V{z.x + beta * po[m].x, z.y + beta * po[m].y};
+        }
+        v[m] = z;
+    }
+    if (valid) {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int n = t + m * G;
+            p[n] = v[m];
+            if (!first) x[n] = xo[m];
+        }
+    }
+    group_fft<M, R, -1, true>(v, t, lds, addr, twM);
+#pragma unroll
+    for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
+    group_sync<true>();
+    V mir[R];
+#pragma unroll
+    for (int m = 0; m < R; m++) mir[m] = lds[addr((M - (t + m * G)) & (M - 1))];
+    if (valid) {
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int k = t + m * G;
+            spec[soff + k] = r2c_post(k, v[m], mir[m], twN[k]);
+        }
+    }
+}
+
 // sigma_v = C_v eps_v for one voxel (Voigt, engineering shear; 21 = upper triangle).
 template <typename T> __device__ __forceinline__ void voigt_stress(const T* __restrict__ c, const T e[6], T s[6])
 {
@@ -449,9 +546,6 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     const V* twL = twsm;
     const T xi1 = (T)(sp.k1 * kx);
     const T xi2 = (T)(sp.k2 * freq_index(ky, sp.n2));
-    T xi3[R];
-#pragma unroll
-    for (int m = 0; m < R; m++) xi3[m] = (T)(sp.k3 * freq_index(t + m * G, sp.n3));
 
     // all three components' loads go out before the first transform (the barriers of
     // the LDS exchanges would otherwise hold each load back behind the previous transform)
@@ -462,8 +556,16 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
         for (int m = 0; m < R; m++) u[j][m] = col[j * NS + (long)(t + m * G) * colstride];
 #pragma unroll
     for (int j = 0; j < 3; j++) group_fft<L, R, -1>(u[j], t, lds, addr, twL);
-    T C[6][6];
+    // beta dt^2 K(xi) + rhobar I with K = N(xi)^T Cbar N(xi), N the Voigt strain of a plane
+    // wave.  At fixed (xi1, xi2) it is quadratic in xi3: N = N12 + xi3 E3 (N12 holds the
+    // xi1, xi2 entries, E3 the unit entries that xi3 multiplies), so
+    //   beta dt^2 K + rhobar I = A0 + xi3 (A1 + xi3 A2)
+    // with A0 = beta dt^2 N12^T C N12 + rhobar I, A1 = beta dt^2 (N12^T C E3 + E3^T C N12),
+    // A2 = beta dt^2 E3^T C E3, formed once per thread (symmetric; upper triangles kept).
+    const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
+    T A0[6], A1[6], A2[6]; // order 00 01 02 11 12 22
     {
+        T C[6][6];
         int o = 0;
 #pragma unroll
         for (int a = 0; a < 6; a++)
@@ -473,48 +575,56 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
                 C[b][a] = (T)sp.Cbar[o];
                 o++;
             }
+        const T x1 = xi1, x2 = xi2;
+        T CN[6][3], CE[6][3];
+#pragma unroll
+        for (int a = 0; a < 6; a++) {
+            CN[a][0] = C[a][0] * x1 + C[a][5] * x2;
+            CN[a][1] = C[a][1] * x2 + C[a][5] * x1;
+            CN[a][2] = C[a][3] * x2 + C[a][4] * x1;
+            CE[a][0] = C[a][4];
+            CE[a][1] = C[a][3];
+            CE[a][2] = C[a][2];
+        }
+        // rows of N12^T X and E3^T X for a 6 x 3 X
+        auto n12 = [&](const T (&X)[6][3], int i, int j) -> T {
+            return i == 0 ? x1 * X[0][j] + x2 * X[5][j] : i == 1 ? x2 * X[1][j] + x1 * X[5][j] : x2 * X[3][j] + x1 * X[4][j];
+        };
+        auto e3 = [&](const T (&X)[6][3], int i, int j) -> T { return i == 0 ? X[4][j] : i == 1 ? X[3][j] : X[2][j]; };
+        int q = 0;
+#pragma unroll
+        for (int i = 0; i < 3; i++)
+#pragma unroll
+            for (int j = i; j < 3; j++) {
+                A0[q] = bdt2 * n12(CN, i, j) + (i == j ? rb : (T)0);
+                A1[q] = bdt2 * (n12(CE, i, j) + e3(CN, i, j));
+                A2[q] = bdt2 * e3(CE, i, j);
+                q++;
+            }
     }
-    const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
     double part = 0.0;
 #pragma unroll
     for (int m = 0; m < R; m++) {
-        const T x1 = xi1, x2 = xi2, x3 = xi3[m];
-        // K = N(xi)^T Cbar N(xi) with N the Voigt strain of a plane wave
-        T CN[6][3];
+        const T x3 = (T)(sp.k3 * freq_index(t + m * G, sp.n3));
+        T K[6];
 #pragma unroll
-        for (int a = 0; a < 6; a++) {
-            CN[a][0] = C[a][0] * x1 + C[a][4] * x3 + C[a][5] * x2;
-            CN[a][1] = C[a][1] * x2 + C[a][3] * x3 + C[a][5] * x1;
-            CN[a][2] = C[a][2] * x3 + C[a][3] * x2 + C[a][4] * x1;
-        }
-        T K[3][3];
-#pragma unroll
-        for (int j = 0; j < 3; j++) {
-            K[0][j] = bdt2 * (x1 * CN[0][j] + x3 * CN[4][j] + x2 * CN[5][j]);
-            K[1][j] = bdt2 * (x2 * CN[1][j] + x3 * CN[3][j] + x1 * CN[5][j]);
-            K[2][j] = bdt2 * (x3 * CN[2][j] + x2 * CN[3][j] + x1 * CN[4][j]);
-        }
-        K[0][0] += rb;
-        K[1][1] += rb;
-        K[2][2] += rb;
+        for (int q = 0; q < 6; q++) K[q] = A0[q] + x3 * (A1[q] + x3 * A2[q]);
+        const T k00 = K[0], k01 = K[1], k02 = K[2], k11 = K[3], k12 = K[4], k22 = K[5];
         V z0, z1, z2;
         if (sp.dim == 2) {
-            const T det = K[0][0] * K[1][1] - K[0][1] * K[1][0];
-            const T id = s / det;
-            z0 = cscale(csub(cscale(u[0][m], K[1][1]), cscale(u[1][m], K[0][1])), id);
-            z1 = cscale(csub(cscale(u[1][m], K[0][0]), cscale(u[0][m], K[1][0])), id);
+            const T id = s / (k00 * k11 - k01 * k01);
+            z0 = cscale(csub(cscale(u[0][m], k11), cscale(u[1][m], k01)), id);
+            z1 = cscale(csub(cscale(u[1][m], k00), cscale(u[0][m], k01)), id);
             z2 = V{0, 0};
         } else {
             // inverse of the symmetric 3x3 by cofactors
-            const T c00 = K[1][1] * K[2][2] - K[1][2] * K[2][1];
-            const T c01 = K[0][2] * K[2][1] - K[0][1] * K[2][2];
-            const T c02 = K[0][1] * K[1][2] - K[0][2] * K[1][1];
-            const T c11 = K[0][0] * K[2][2] - K[0][2] * K[2][0];
-            const T c12 = K[0][2] * K[1][0] - K[0][0] * K[1][2];
-            const T c22 = K[0][0] * K[1][1] - K[0][1] * K[1][0];
-            const T det = K[0][0] * c00 + K[0][1] * (K[1][2] * K[2][0] - K[1][0] * K[2][2]) +
-                          K[0][2] * (K[1][0] * K[2][1] - K[1][1] * K[2][0]);
-            const T id = s / det;
+            const T c00 = k11 * k22 - k12 * k12;
+            const T c01 = k02 * k12 - k01 * k22;
+            const T c02 = k01 * k12 - k02 * k11;
+            const T c11 = k00 * k22 - k02 * k02;
+            const T c12 = k02 * k01 - k00 * k12;
+            const T c22 = k00 * k11 - k01 * k01;
+            const T id = s / (k00 * c00 + k01 * c01 + k02 * c02);
             const V r0 = u[0][m], r1 = u[1][m], r2 = u[2][m];
             z0 = cscale(cadd(cadd(cscale(r0, c00), cscale(r1, c01)), cscale(r2, c02)), id);
             z1 = cscale(cadd(cadd(cscale(r0, c01), cscale(r1, c11)), cscale(r2, c12)), id);
@@ -555,7 +665,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
 // trips along one axis: forward FFT, i xi / n, inverse FFT.  Every element is
 // read and written by the thread that owns its row in the FFT register layout.
 // ---------------------------------------------------------------------------
-template <typename T, int L, int R, int OP, int BLK, int TXC>
+template <typename T, int L, int R, int OP, int BLK, int TXC, bool PF>
 __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>* __restrict__ S2, long rowstride,
                                                long cs, int TXr, SpecParams sp, const cx_t<T>* __restrict__ tw)
 {
@@ -576,8 +686,16 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
     // rowstride is the plane (kz) stride of the layout
     const long start = YAX ? (long)blockIdx.y * rowstride : (long)blockIdx.y * M;
     const long step = YAX ? (long)M : rowstride;
+#if NM_COL_OFF32
+    // uniform tile bases (scalar registers) plus 32-bit per-lane byte offsets
+    V* const s1 = S + start + (long)blockIdx.x * TX;
+    V* const s2 = S2 + start + (long)blockIdx.x * TX;
+    const uint32_t lane = (uint32_t)(c * sizeof(V)) + (uint32_t)t * (uint32_t)(step * sizeof(V));
+    const uint32_t mstep = (uint32_t)(G * step * sizeof(V));
+#else
     V* s1 = S + start + kx;
     V* s2 = S2 + start + kx;
+#endif
     ColAddrT<TXC> addr{c, TX};
     const V* twL = twsm;
     const T xi1 = (T)(sp.k1 * kx);
@@ -586,6 +704,18 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
     T mul[R];
 #pragma unroll
     for (int m = 0; m < R; m++) mul[m] = (T)(kax * freq_index(t + m * G, n));
+#if NM_COL_OFF32
+    auto ld = [&](const V* base, int comp, V (&v)[R]) {
+        const char* p = (const char*)(base + comp * cs);
+#pragma unroll
+        for (int m = 0; m < R; m++) v[m] = *(const V*)(p + (lane + (uint32_t)m * mstep));
+    };
+    auto st = [&](V* base, int comp, const V (&v)[R]) {
+        char* p = (char*)(base + comp * cs);
+#pragma unroll
+        for (int m = 0; m < R; m++) *(V*)(p + (lane + (uint32_t)m * mstep)) = v[m];
+    };
+#else
     auto ld = [&](const V* col, int comp, V (&v)[R]) {
 #pragma unroll
         for (int m = 0; m < R; m++) v[m] = col[comp * cs + (long)(t + m * G) * step];
@@ -594,6 +724,7 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
 #pragma unroll
         for (int m = 0; m < R; m++) col[comp * cs + (long)(t + m * G) * step] = v[m];
     };
+#endif
     // v <- D v along the column (forward FFT, i xi / n, inverse FFT)
     auto deriv = [&](V (&v)[R]) {
         group_fft<L, R, -1>(v, t, lds, addr, twL);
@@ -601,7 +732,93 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
         for (int m = 0; m < R; m++) v[m] = ZOps<T>::iscale(v[m], mul[m]);
         group_fft<L, R, +1>(v, t, lds, addr, twL);
     };
-    if constexpr (OP == YOP_DERIV) {
+    // Software-pipelined order (PF): the loads of the next operands are issued before a
+    // transform so that they are in flight while it runs (the LDS barriers of the
+    // transforms do not wait on global loads); it holds up to three operand tiles.
+    if constexpr (PF && OP == YOP_DERIV) {
+        V cur[R], nxt[R];
+        ld(s1, 0, nxt);
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+#pragma unroll
+            for (int m = 0; m < R; m++) cur[m] = nxt[m];
+            if (j < 2) ld(s1, j + 1, nxt);
+            deriv(cur);
+            st(s1, 3 + j, cur);
+        }
+    } else if constexpr (PF && OP == YOP_DIV) {
+        // sigma Voigt 0..5 = s11 s22 s33 s23 s13 s12
+        V a[R], b[R], c[R];
+        ld(s2, 1, a); // s22
+        ld(s2, 5, b); // s12
+        ld(s2, 0, c); // s11
+        deriv(a);
+#pragma unroll
+        for (int m = 0; m < R; m++) a[m] = cadd(a[m], ZOps<T>::iscale(b[m], xi1));
+        st(s1, 1, a);
+        ld(s2, 3, a); // s23
+        deriv(b);
+#pragma unroll
+        for (int m = 0; m < R; m++) b[m] = cadd(b[m], ZOps<T>::iscale(c[m], xi1));
+        st(s1, 0, b);
+        ld(s2, 4, c); // s13
+        deriv(a);
+#pragma unroll
+        for (int m = 0; m < R; m++) a[m] = cadd(a[m], ZOps<T>::iscale(c[m], xi1));
+        st(s1, 2, a);
+    } else if constexpr (PF && OP == ZOP_STRAIN) {
+        const T sc = (T)sp.inv_n1;
+        V a[R], b[R], c[R];
+        ld(s1, 0, a); // U1
+        ld(s1, 2, b); // U3
+        ld(s1, 1, c); // U2
+        {
+            V d[R];
+#pragma unroll
+            for (int m = 0; m < R; m++) d[m] = cscale(ZOps<T>::iscale(a[m], xi1), sc);
+            st(s2, 0, d); // eps11
+        }
+        deriv(a); // D_z U1
+#pragma unroll
+        for (int m = 0; m < R; m++) a[m] = cscale(cadd(a[m], ZOps<T>::iscale(b[m], xi1)), sc);
+        st(s2, 4, a); // g13
+        ld(s1, 3, a); // D_y U1
+        deriv(b);     // D_z U3
+#pragma unroll
+        for (int m = 0; m < R; m++) b[m] = cscale(b[m], sc);
+        st(s2, 2, b); // eps33
+        ld(s1, 5, b); // D_y U3
+#pragma unroll
+        for (int m = 0; m < R; m++) a[m] = cscale(cadd(a[m], ZOps<T>::iscale(c[m], xi1)), sc);
+        st(s2, 5, a); // g12
+        ld(s1, 4, a); // D_y U2
+        deriv(c);     // D_z U2
+#pragma unroll
+        for (int m = 0; m < R; m++) c[m] = cscale(cadd(c[m], b[m]), sc);
+        st(s2, 3, c); // g23
+#pragma unroll
+        for (int m = 0; m < R; m++) a[m] = cscale(a[m], sc);
+        st(s2, 1, a); // eps22
+    } else if constexpr (PF && OP == ZOP_DIVZ) {
+        const T cd = (T)(-sp.bdt2 * sp.inv_n1);
+        constexpr int SRC[3] = {4, 3, 2};
+        V v[R], w[R], vn[R];
+        ld(s2, SRC[0], v);
+        ld(s1, 0, w);
+#pragma unroll
+        for (int j = 0; j < 3; j++) {
+            if (j < 2) ld(s2, SRC[j + 1], vn);
+            deriv(v);
+#pragma unroll
+            for (int m = 0; m < R; m++) v[m] = cscale(cadd(v[m], w[m]), cd);
+            st(s1, j, v);
+            if (j < 2) {
+                ld(s1, j + 1, w);
+#pragma unroll
+                for (int m = 0; m < R; m++) v[m] = vn[m];
+            }
+        }
+    } else if constexpr (OP == YOP_DERIV) {
 #pragma unroll 1
         for (int j = 0; j < 3; j++) {
             V v[R];
@@ -756,6 +973,17 @@ template <typename T> int launch_xinv(int mode, int n1, const XInvArgs& a, const
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+template <typename T> int launch_xpupdate(int n1, const XInvArgs& a, const void* tw, hipStream_t s)
+{
+    const int blocks = xinv_blocks(n1, a.nlines);
+    const cx_t<T>* t = (const cx_t<T>*)tw;
+    NM_SIZE_SWITCH(n1, {
+        constexpr int M = NN / 2, R = (M >= 8 ? 8 : M);
+        hipLaunchKernelGGL((k_xpupdate<T, NN, R>), dim3(blocks), dim3(kBlock), 0, s, a, t);
+    })
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 template <typename T>
 int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* phase, const void* C21, const void* tw,
                    hipStream_t s)
@@ -787,13 +1015,16 @@ int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* ph
 #ifndef NM_ZSPEC_BLK64
 #define NM_ZSPEC_BLK64 256
 #endif
+#ifndef NM_ZSPEC_BLK32
+#define NM_ZSPEC_BLK32 256
+#endif
 
 template <int L> constexpr int ypass_radix() { return L >= 16 ? 16 : L; }
 template <typename T, int L> constexpr int zspec_radix()
 {
     return L < 8 ? L : (sizeof(T) == 8 ? (NM_ZSPEC_R64 < L ? NM_ZSPEC_R64 : L) : (NM_ZSPEC_R32 < L ? NM_ZSPEC_R32 : L));
 }
-template <typename T> constexpr int zspec_block() { return sizeof(T) == 8 ? NM_ZSPEC_BLK64 : 256; }
+template <typename T> constexpr int zspec_block() { return sizeof(T) == 8 ? NM_ZSPEC_BLK64 : NM_ZSPEC_BLK32; }
 
 
 template <typename T>
@@ -880,6 +1111,13 @@ int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, con
 #ifndef NM_COLOP_R64
 #define NM_COLOP_R64 16
 #endif
+// Software-pipelined column operators (three operand tiles per thread).
+#ifndef NM_COLOP_PF32
+#define NM_COLOP_PF32 1
+#endif
+#ifndef NM_COLOP_PF64
+#define NM_COLOP_PF64 0
+#endif
 template <typename T, int L> constexpr int colop_radix()
 {
     return L < 16 ? L : (sizeof(T) == 8 ? (NM_COLOP_R64 < L ? NM_COLOP_R64 : L) : 16);
@@ -890,20 +1128,21 @@ static void colop_dispatch(int op, dim3 grid, dim3 block, hipStream_t s, cx_t<T>
                            long cs, int TX, const SpecParams& sp, const cx_t<T>* t)
 {
     constexpr int R = colop_radix<T, L>();
+    constexpr bool PF = sizeof(T) == 8 ? NM_COLOP_PF64 : NM_COLOP_PF32;
     switch (op) {
     case YOP_DERIV:
-        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DERIV, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
+        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DERIV, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
                            t);
         break;
     case YOP_DIV:
-        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DIV, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp, t);
+        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DIV, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp, t);
         break;
     case ZOP_STRAIN:
-        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_STRAIN, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
+        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_STRAIN, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
                            t);
         break;
     default:
-        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_DIVZ, 256, TXC>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
+        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_DIVZ, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
                            t);
         break;
     }
@@ -940,6 +1179,7 @@ int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, v
 #define NM_INST(T)                                                                                                     \
     template int launch_xfwd<T>(int, int, const XFwdArgs&, const void*, hipStream_t);                                  \
     template int launch_xinv<T>(int, int, const XInvArgs&, const void*, hipStream_t);                                  \
+    template int launch_xpupdate<T>(int, const XInvArgs&, const void*, hipStream_t);                                   \
     template int launch_xstress<T>(int, void*, const SpecLayout&, const uint16_t*, const void*, const void*,          \
                                    hipStream_t);                                                                       \
     template int launch_ypass<T>(int, int, const SpecLayout&, void*, const void*, hipStream_t);                        \
