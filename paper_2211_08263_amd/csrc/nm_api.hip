@@ -63,7 +63,7 @@ struct nm_ctx {
     double2* spec64 = nullptr;
     double2* spec64b = nullptr;
     // FP32 fields
-    float *d32 = nullptr, *rhs32 = nullptr, *r32 = nullptr, *z32 = nullptr, *p32 = nullptr, *q32 = nullptr;
+    float *d32 = nullptr, *r32 = nullptr, *p32 = nullptr, *q32 = nullptr;
     float2* spec32 = nullptr;
     float2* spec32b = nullptr;
     // Gamma buffers
@@ -276,9 +276,11 @@ struct PcgResult {
 
 // Preconditioned conjugate gradients (Hestenes-Stiefel) on real-space vectors.
 // x: initial guess / solution.  With masked, P A P and P M P on the free dofs.
-// rr_known >= 0: r already holds P (rhs - A x) with r.r = rr_known (no initial apply).
+// rr_known >= 0: r already holds P (rhs - A x) with r.r = rr_known (no initial apply;
+// rhs may then be null).  The preconditioned residual z lives only as the x spectrum
+// between the preconditioner's z pass and the next direction update.
 template <typename T>
-int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool x_zero, double bref, double tol,
+int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* p, T* q, bool masked, bool x_zero, double bref, double tol,
         int max_iter, int fixed_iters, bool allow_unconverged, PcgResult* res, double rr_known = -1.0)
 {
     hipStream_t s = c->stream;
@@ -287,6 +289,7 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* z, T* p, T* q, bool masked, bool
     void* spec = Prec<T>::spec(c);
     // r = P (b - A x)
     double rr = rr_known;
+    if (rr_known < 0 && !rhs) return fail(c, NM_EINVAL, "PCG needs the right-hand side or the initial residual");
     if (rr_known < 0) {
         if (x_zero) LCHK(c, launch_fill<T>(q, (T)0, n, s));
         else CHK(apply_A<T>(c, x, q, mk));
@@ -475,14 +478,16 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
             return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps (rel %.3g)", c->opt.tol,
                         sweeps, std::sqrt(rr) / bref);
         small_update = !approx && std::sqrt(rr) <= kSmallUpdate * c->opt.tol * bref;
-        LCHK(c, launch_cast_d2f(c->rhs32, c->r, n, s));
+        // the correction starts at zero, so its residual is r itself (already P-projected):
+        // the FP32 solve starts from the rounded copy with the FP64 r.r
+        LCHK(c, launch_cast_d2f(c->r32, c->r, n, s));
         LCHK(c, launch_fill<float>(c->d32, 0.0f, n, s));
         PcgResult pr;
         // reduce the residual only as far as the outer tolerance still needs (half of the
         // remaining factor), but never ask FP32 for more than inner_tol
         const double need = 0.5 * c->opt.tol * bref / std::sqrt(rr);
-        CHK(pcg<float>(c, c->rhs32, c->d32, c->r32, c->z32, c->p32, c->q32, true, true, std::sqrt(rr),
-                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr));
+        CHK(pcg<float>(c, nullptr, c->d32, c->r32, c->p32, c->q32, true, true, std::sqrt(rr),
+                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr, rr));
         inner += pr.iters;
         LCHK(c, launch_add_f2d(x, c->d32, n, s));
         sweeps++;
@@ -563,7 +568,7 @@ int build_green(nm_ctx* c)
             LCHK(c, launch_set_gamma(c->b, c->gidx + pnt, 1, c->Ubuf, 0, 3, c->N, s));
             LCHK(c, launch_fill<double>(c->w, 0.0, n, s));
             PcgResult pr;
-            CHK(pcg<double>(c, c->b, c->w, c->r, c->z, c->p, c->q, false, true, 1.0, c->opt.green_tol,
+            CHK(pcg<double>(c, c->b, c->w, c->r, c->p, c->q, false, true, 1.0, c->opt.green_tol,
                             c->opt.max_iter, -1, false, &pr));
             LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));
             HIPCHK(c, hipMemcpyAsync(col.data(), c->gbuf, 3 * c->ng * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -877,7 +882,7 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     CHK(dalloc(c, &c->spec32, 6 * c->lay.cs));
     CHK(dalloc(c, &c->spec32b, 6 * c->lay.cs));
     if (c->opt.precision == NM_PREC_MIXED) {
-        float** f32[] = {&c->d32, &c->rhs32, &c->r32, &c->z32, &c->p32, &c->q32};
+        float** f32[] = {&c->d32, &c->r32, &c->p32, &c->q32};
         for (float** f : f32) {
             CHK(dalloc(c, f, n));
             LCHK(c, launch_fill<float>(*f, 0.0f, n, s));
@@ -965,7 +970,7 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         double bn;
         CHK(norm2<double>(c, c->b, &bn));
         PcgResult r1, r2;
-        CHK(pcg<double>(c, c->b, c->w, c->r, c->z, c->p, c->q, false, false, std::sqrt(bn), c->opt.tol,
+        CHK(pcg<double>(c, c->b, c->w, c->r, c->p, c->q, false, false, std::sqrt(bn), c->opt.tol,
                         c->opt.max_iter, -1, false, &r1));
         // V = U - u_b on Gamma ; F = G^-1 V / (beta dt^2)   (eqs. Vt, L-determination_ND)
         std::vector<double> g3(3 * c->ng), F(nd);
@@ -988,7 +993,7 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         LCHK(c, launch_fill<double>(c->b, 0.0, n, s));
         HIPCHK(c, hipMemcpyAsync(c->gbuf, F3.data(), F3.size() * sizeof(double), hipMemcpyHostToDevice, s));
         LCHK(c, launch_set_gamma(c->b, c->gidx, c->ng, c->gbuf, 1, 3, c->N, s));
-        CHK(pcg<double>(c, c->b, c->uf, c->r, c->z, c->p, c->q, false, false, std::sqrt(fn), c->opt.tol,
+        CHK(pcg<double>(c, c->b, c->uf, c->r, c->p, c->q, false, false, std::sqrt(fn), c->opt.tol,
                         c->opt.max_iter, -1, false, &r2));
         // u_n = u_b + beta dt^2 u_f   (eq. Sol_Real_ND)
         LCHK(c, launch_axpby<double>(c->w, c->w, c->uf, c->sp.bdt2, n, s));
@@ -1010,7 +1015,7 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
             CHK(solve_mixed(c, c->w, bref, &local, rr0));
         } else {
             PcgResult r1;
-            CHK(pcg<double>(c, c->b, c->w, c->r, c->z, c->p, c->q, true, false, bref, c->opt.tol, c->opt.max_iter,
+            CHK(pcg<double>(c, c->b, c->w, c->r, c->p, c->q, true, false, bref, c->opt.tol, c->opt.max_iter,
                             -1, false, &r1, rr0));
             local.iters[0] = r1.iters;
             local.relres = std::sqrt(r1.rr) / (bref > 0 ? bref : 1.0);
@@ -1091,7 +1096,7 @@ int nm_pcg_solve(nm_ctx* c, const void* b_dev, void* x_dev, int masked, double t
         bref = std::sqrt(bn);
     }
     PcgResult pr;
-    CHK(pcg<double>(c, c->b, (double*)x_dev, c->r, c->z, c->p, c->q, masked != 0, false, bref, tol, max_iter,
+    CHK(pcg<double>(c, c->b, (double*)x_dev, c->r, c->p, c->q, masked != 0, false, bref, tol, max_iter,
                     fixed_iters, false, &pr));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     if (iters) *iters = pr.iters;

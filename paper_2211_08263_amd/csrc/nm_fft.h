@@ -145,9 +145,77 @@ template <int L, int R> struct FftShape {
     static_assert(L % R == 0, "L must be a multiple of R");
 };
 
+// Twiddle sources.  The stage of span Ns and radix Rs multiplies input r of butterfly
+// b (j = t + b G, k = j mod Ns) by w_L^(r k L / (Ns Rs)), w_L = exp(-2 pi i / L); the
+// inverse transform takes the conjugate.
+// TwTable reads the table w_L^i, i < L (in LDS); TwRegs holds the values a thread needs
+// for all stages in registers, read once from the table, for kernels that run many
+// transforms of one length.
+template <typename V> struct TwTable {
+    const V* p;
+    template <int L, int Ns, int Rs> __device__ __forceinline__ V get(int, int r, int k) const
+    {
+        return p[r * k * (L / (Ns * Rs))];
+    }
+};
+
+template <int L, int R> struct FftPlan {
+    // twiddles per thread of the stages from span Ns on
+    static constexpr int count_from(int Ns)
+    {
+        int c = 0;
+        while (Ns < L) {
+            const int Rs = (Ns * R <= L) ? R : (L / Ns);
+            if (Ns > 1) c += (R / Rs) * (Rs - 1);
+            Ns *= Rs;
+        }
+        return c;
+    }
+    static constexpr int count() { return count_from(1); }
+    // index of the first twiddle of the stage of span Ns
+    static constexpr int offset(int Ns) { return count() - count_from(Ns); }
+};
+
+template <int L, int R, typename V> struct TwRegs {
+    using Plan = FftPlan<L, R>;
+    using S = decltype(V{}.x);
+    // clang vector element (an array of HIP's vector structs would stay in scratch memory)
+    typedef S E __attribute__((ext_vector_type(2)));
+    static constexpr int NT = Plan::count() > 0 ? Plan::count() : 1;
+    E w[NT];
+    template <int Ns> __device__ __forceinline__ void load_from(int t, const V* __restrict__ tab)
+    {
+        if constexpr (Ns < L) {
+            constexpr int Rs = (Ns * R <= L) ? R : (L / Ns);
+            constexpr int G = L / R, NB = R / Rs;
+            if constexpr (Ns > 1) {
+                constexpr int o = Plan::offset(Ns);
+#pragma unroll
+                for (int b = 0; b < NB; b++) {
+                    const int k = (t + b * G) & (Ns - 1);
+#pragma unroll
+                    for (int r = 1; r < Rs; r++) {
+                        const V x = tab[r * k * (L / (Ns * Rs))];
+                        w[o + b * (Rs - 1) + r - 1] = E{x.x, x.y};
+                    }
+                }
+            }
+            load_from<Ns * Rs>(t, tab);
+        }
+    }
+    __device__ __forceinline__ void load(int t, const V* __restrict__ tab) { load_from<1>(t, tab); }
+    template <int LL, int Ns, int Rs> __device__ __forceinline__ V get(int b, int r, int) const
+    {
+        static_assert(LL == L, "twiddle cache of another length");
+        constexpr int o = Plan::offset(Ns);
+        const E x = w[o + b * (Rs - 1) + r - 1];
+        return V{x.x, x.y};
+    }
+};
+
 // One Stockham stage (radix chosen from Ns) followed by the remaining stages.
-template <int L, int R, int DIR, int Ns, bool WAVE, typename V, typename Addr>
-__device__ __forceinline__ void fft_stage(V (&v)[R], int t, V* lds, const Addr& addr, const V* __restrict__ tw)
+template <int L, int R, int DIR, int Ns, bool WAVE, typename V, typename Addr, typename Tw>
+__device__ __forceinline__ void fft_stage(V (&v)[R], int t, V* lds, const Addr& addr, const Tw& tw)
 {
     if constexpr (Ns < L) {
         constexpr int Rs = (Ns * R <= L) ? R : (L / Ns);
@@ -170,9 +238,8 @@ __device__ __forceinline__ void fft_stage(V (&v)[R], int t, V* lds, const Addr& 
             if constexpr (Ns > 1) {
 #pragma unroll
                 for (int r = 1; r < Rs; r++) {
-                    V w = tw[r * k * (L / (Ns * Rs))];
-                    if constexpr (DIR > 0) w.y = -w.y;
-                    a[r] = cmul(a[r], w);
+                    const V w = tw.template get<L, Ns, Rs>(b, r, k);
+                    a[r] = DIR > 0 ? cmulc(a[r], w) : cmul(a[r], w);
                 }
             }
             Dft<Rs, DIR, V>::run(a);
@@ -190,14 +257,20 @@ __device__ __forceinline__ void fft_stage(V (&v)[R], int t, V* lds, const Addr& 
     }
 }
 
-// Length-L transform of the group's sequence (see file comment).  tw points
-// at the table w_L^i = exp(-2 pi i i / L), i < L.  Every thread of the block
-// must call it (it contains block barriers); on exit the LDS area is free.
-template <int L, int R, int DIR, bool WAVE = false, typename V, typename Addr>
-__device__ __forceinline__ void group_fft(V (&v)[R], int t, V* lds, const Addr& addr, const V* __restrict__ tw)
+// Length-L transform of the group's sequence (see file comment).  tw is a twiddle
+// source (group_fft_tw) or points at the table w_L^i = exp(-2 pi i i / L), i < L.  Every
+// thread of the block must call it (it contains block barriers); on exit the LDS
+// area is free.
+template <int L, int R, int DIR, bool WAVE = false, typename V, typename Addr, typename Tw>
+__device__ __forceinline__ void group_fft_tw(V (&v)[R], int t, V* lds, const Addr& addr, const Tw& tw)
 {
     // The last stage's LDS reads are followed by a sync, so no trailing one is needed.
     if constexpr (L > 1) fft_stage<L, R, DIR, 1, WAVE>(v, t, lds, addr, tw);
+}
+template <int L, int R, int DIR, bool WAVE = false, typename V, typename Addr>
+__device__ __forceinline__ void group_fft(V (&v)[R], int t, V* lds, const Addr& addr, const V* tw)
+{
+    group_fft_tw<L, R, DIR, WAVE>(v, t, lds, addr, TwTable<V>{tw});
 }
 
 // Offset of the table of length L (L = 2, 4, ..., 1024) inside the packed
