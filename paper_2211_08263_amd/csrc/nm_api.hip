@@ -69,7 +69,9 @@ struct nm_ctx {
     // Gamma buffers
     double* Ubuf = nullptr; // dim * max(ng, 1)
     double* lift = nullptr; // projected route: A e_c, e_c = unit component c on Gamma (3 x (3 x N))
-    bool pred_ready = false; // ut and b hold the predictor of the coming step
+    bool pred_ready = false; // ut and b hold the predictor of the coming step (and winc its scale sums)
+    double* winc = nullptr;  // per-block sums of |u~ - u_n|^2 from the fused corrector
+    bool d32_is_x = false;   // d32 holds the FP32 copy of the initial iterate (learned start)
     double* gbuf = nullptr; // dim * max(ng, 1)
     std::vector<double> G, LU, F_last;
     std::vector<int> piv;
@@ -457,7 +459,8 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
             // the first residual only seeds the first correction, whose own accuracy is
             // about inner_tol, so the FP32 operator serves; every later residual (and the
             // stopping test) is FP64
-            LCHK(c, launch_cast_d2f(c->d32, x, n, s));
+            if (!c->d32_is_x) LCHK(c, launch_cast_d2f(c->d32, x, n, s));
+            c->d32_is_x = false;
             CHK(apply_A<float>(c, c->d32, c->q32, c->mask));
             LCHK(c, launch_residual_f32q(c->b, c->q32, c->r, c->mask, c->N, c->part_a, s));
             LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
@@ -866,6 +869,7 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     c->npart = std::max({xfwd_blocks(c->n1, 3L * c->n2 * c->n3), vec_blocks(n), zprecond_blocks<double>(c->sp),
                          zprecond_blocks<float>(c->sp)});
     CHK(dalloc(c, &c->part_a, c->npart));
+    CHK(dalloc(c, &c->winc, vec_blocks(3 * c->N)));
     CHK(dalloc(c, &c->part_b, c->npart));
     // fields
     double** f64[] = {&c->u, &c->v, &c->a, &c->ut, &c->b, &c->w, &c->r, &c->z, &c->p, &c->q};
@@ -944,9 +948,11 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     auto t0 = std::chrono::steady_clock::now();
     // predictor and right-hand side, eq. (Fourier_ND_b) (already formed by the previous
     // step's corrector unless the state or b changed since)
+    const bool inc_ok = c->pred_ready;
     if (!c->pred_ready)
         LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
     c->pred_ready = false;
+    c->d32_is_x = false;
     // initial guess
     double t_warm = 0;
     switch (c->opt.warm_start) {
@@ -955,7 +961,18 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     case NM_WS_LEARNED: {
         if (!c->net) return fail(c, NM_EINVAL, "learned warm start requested but no network is attached");
         auto tw0 = std::chrono::steady_clock::now();
-        int e = nm::warm_predict(c->net, warm_args(c), c->w, s);
+        nm::WarmArgs wa = warm_args(c);
+        if (inc_ok) {
+            // the corrector of the previous step already summed |u~ - u_n|^2
+            wa.inc = c->winc;
+            wa.inc_nb = vec_blocks(n);
+        }
+        if (c->opt.precision == NM_PREC_MIXED) {
+            // the first refinement sweep starts from the FP32 copy
+            wa.x0f = c->d32;
+            c->d32_is_x = true;
+        }
+        int e = nm::warm_predict(c->net, wa, c->w, s);
         if (e) return fail(c, e == -1 ? NM_EUNSUPPORTED : NM_EHIP, "warm-start network failed");
         HIPCHK(c, hipStreamSynchronize(s));
         t_warm = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - tw0).count();
@@ -1004,6 +1021,8 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         c->F_last = F;
     } else {
         if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
+        if (c->ng > 0 && c->d32_is_x)
+            LCHK(c, launch_set_gamma_f32(c->d32, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
         // reference residual r_bar = P (b - A u_bar) (left in c->r); from the lifting
         // responses when U is uniform on Gamma
         double bref;
@@ -1043,7 +1062,7 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     // corrector, fused with the predictor and right-hand side of the next step; then
     // u <- u_n (pointer swap)
     LCHK(c, launch_corrector_predictor(c->w, c->ut, c->v, c->a, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta,
-                                       c->gam, s));
+                                       c->gam, c->winc, s));
     std::swap(c->u, c->w);
     HIPCHK(c, hipStreamSynchronize(s));
     c->pred_ready = true;

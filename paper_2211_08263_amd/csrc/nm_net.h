@@ -28,6 +28,9 @@ struct WarmArgs {
     uint16_t* feat;        // BF16 [N][32]
     float* l0mat;          // FP32 [N][16]: material share of layer 0 (with its bias)
     unsigned long long* l0mat_version; // network version l0mat was computed for (0: none)
+    const double* inc = nullptr; // per-block sums of |u~ - u_n|^2 left by the corrector (null: summed here)
+    int inc_nb = 0;              // number of those sums
+    float* x0f = nullptr;        // warm_predict: FP32 copy of x0 as well (or null)
 };
 
 int warm_features(const WarmArgs& a, hipStream_t s);

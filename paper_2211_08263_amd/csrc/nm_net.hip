@@ -444,14 +444,16 @@ __global__ __launch_bounds__(256) void k_incr_norm(const double* __restrict__ ut
     if (threadIdx.x == 0) partials[blockIdx.x] = sh[0] + sh[1] + sh[2] + sh[3];
 }
 
-__global__ void k_sum_scale(const double* __restrict__ partials, int n, long count, double* scale)
+// scale = sqrt(sum of the partials / count); one wavefront, fixed summation order
+__global__ __launch_bounds__(64) void k_sum_scale(const double* __restrict__ partials, int n, long count,
+                                                  double* scale)
 {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
-        double s = 0.0;
-        for (int i = 0; i < n; i++) s += partials[i];
-        // s = 0 before anything moves: features are zero and the correction vanishes
-        scale[0] = sqrt(s / (double)count);
-    }
+    double s = 0.0;
+    for (int i = threadIdx.x; i < n; i += 64) s += partials[i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o, 64);
+    // s = 0 before anything moves: features are zero and the correction vanishes
+    if (threadIdx.x == 0) scale[0] = sqrt(s / (double)count);
 }
 
 __global__ __launch_bounds__(256) void k_features(const double* __restrict__ u, const double* __restrict__ v,
@@ -528,14 +530,19 @@ __global__ __launch_bounds__(256) void k_features_material(const uint16_t* __res
     }
 }
 
-// x0 = u~ + s * pred (SoA FP64 out)
+// x0 = u~ + s * pred (SoA FP64 out; x0f, if given, receives the FP32 copy)
 __global__ __launch_bounds__(256) void k_predict(const double* __restrict__ ut, const float* __restrict__ pred,
-                                                 const double* __restrict__ scale, double* __restrict__ x0, long N)
+                                                 const double* __restrict__ scale, double* __restrict__ x0,
+                                                 float* __restrict__ x0f, long N)
 {
     const double s = scale[0];
     for (long v = (long)blockIdx.x * blockDim.x + threadIdx.x; v < N; v += (long)gridDim.x * blockDim.x)
 #pragma unroll
-        for (int c = 0; c < 3; c++) x0[c * N + v] = ut[c * N + v] + s * (double)pred[v * kPredStride + c];
+        for (int c = 0; c < 3; c++) {
+            const double x = ut[c * N + v] + s * (double)pred[v * kPredStride + c];
+            x0[c * N + v] = x;
+            if (x0f) x0f[c * N + v] = (float)x;
+        }
 }
 
 // target = (u_next - u~) / s = beta dt^2 a_next / s  (the corrector's definition of
@@ -991,8 +998,12 @@ int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
         *a.l0mat_version = net->version;
     }
     const long n = 3 * a.N;
-    hipLaunchKernelGGL(k_incr_norm, dim3(512), dim3(256), 0, s, a.ut, a.u, n, a.red);
-    hipLaunchKernelGGL(k_sum_scale, dim3(1), dim3(64), 0, s, a.red, 512, n, a.scale);
+    if (a.inc) {
+        hipLaunchKernelGGL(k_sum_scale, dim3(1), dim3(64), 0, s, a.inc, a.inc_nb, n, a.scale);
+    } else {
+        hipLaunchKernelGGL(k_incr_norm, dim3(512), dim3(256), 0, s, a.ut, a.u, n, a.red);
+        hipLaunchKernelGGL(k_sum_scale, dim3(1), dim3(64), 0, s, a.red, 512, n, a.scale);
+    }
     hipLaunchKernelGGL(k_features_state, dim3(2048), dim3(256), 0, s, a.u, a.v, a.a, a.dt, a.c2, a.N, a.scale,
                        a.feat);
     if (launch_conv(16, EPI_BF16_ACT_ADD, a.feat, net->wf0s, nullptr, net->act[1], a.l0mat, g, 16, 16, s)) return -2;
@@ -1006,7 +1017,7 @@ int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
                             s);
         if (e) return -2;
     }
-    hipLaunchKernelGGL(k_predict, dim3(2048), dim3(256), 0, s, a.ut, net->pred, a.scale, x0, a.N);
+    hipLaunchKernelGGL(k_predict, dim3(2048), dim3(256), 0, s, a.ut, net->pred, a.scale, x0, a.x0f, a.N);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -563,7 +563,11 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     const int tid = threadIdx.x, c = tid % TX, t = tid / TX;
     const int M = sp.n1 / 2;
     const int kx = blockIdx.x * TX + c, ky = blockIdx.y;
-    V* col = data + (long)ky * M + kx;
+    // uniform column-tile base (scalar registers) plus 32-bit per-lane byte offsets
+    V* const cb = data + (long)ky * M + (long)blockIdx.x * TX;
+    const uint32_t lane = (uint32_t)(c * sizeof(V)) + (uint32_t)t * (uint32_t)(colstride * sizeof(V));
+    const uint32_t mstep = (uint32_t)(G * colstride * sizeof(V));
+    auto at = [&](int j, int m) -> V& { return *(V*)((char*)(cb + j * NS) + (lane + (uint32_t)m * mstep)); };
     ColAddrT<TXC> addr{c, TX};
     const V* twL = twsm;
     const T xi1 = (T)(sp.k1 * kx);
@@ -575,7 +579,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
 #pragma unroll
     for (int j = 0; j < 3; j++)
 #pragma unroll
-        for (int m = 0; m < R; m++) u[j][m] = col[j * NS + (long)(t + m * G) * colstride];
+        for (int m = 0; m < R; m++) u[j][m] = at(j, m);
 #pragma unroll
     for (int j = 0; j < 3; j++) group_fft<L, R, -1>(u[j], t, lds, addr, twL);
     // beta dt^2 K(xi) + rhobar I with K = N(xi)^T Cbar N(xi), N the Voigt strain of a plane
@@ -624,7 +628,9 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
                 q++;
             }
     }
-    double part = 0.0;
+    // per-thread part of r . z in the working precision (24 products at most), summed in
+    // FP64 across threads
+    T part = 0;
 #pragma unroll
     for (int m = 0; m < R; m++) {
         const T x3 = (T)(sp.k3 * freq_index(t + m * G, sp.n3));
@@ -655,17 +661,17 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
         // r . z by Parseval on the half spectrum: bins 0 < kx < n1/2 stand for themselves
         // and their mirrors (weight 2); the packed slot kx = 0 holds the kx = 0 and
         // kx = n1/2 planes, whose cross terms are imaginary (weight 1, real part)
-        part += (kx == 0 ? 1.0 : 2.0) *
-                ((double)u[0][m].x * z0.x + (double)u[0][m].y * z0.y + (double)u[1][m].x * z1.x +
-                 (double)u[1][m].y * z1.y + (double)u[2][m].x * z2.x + (double)u[2][m].y * z2.y);
+        part += u[0][m].x * z0.x + u[0][m].y * z0.y + u[1][m].x * z1.x + u[1][m].y * z1.y + u[2][m].x * z2.x +
+                u[2][m].y * z2.y;
         u[0][m] = z0;
         u[1][m] = z1;
         u[2][m] = z2;
     }
     if (partials) {
         __shared__ double red[BLK / 64 > 0 ? BLK / 64 : 1];
-        part = wave_sum(part);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = part;
+        double pd = (kx == 0 ? 1.0 : 2.0) * (double)part;
+        pd = wave_sum(pd);
+        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pd;
         __syncthreads();
         if (threadIdx.x == 0) {
             double tot = 0.0;
@@ -677,7 +683,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     for (int j = 0; j < 3; j++) {
         group_fft<L, R, +1>(u[j], t, lds, addr, twL);
 #pragma unroll
-        for (int m = 0; m < R; m++) col[j * NS + (long)(t + m * G) * colstride] = u[j][m];
+        for (int m = 0; m < R; m++) at(j, m) = u[j][m];
     }
 }
 

@@ -47,6 +47,8 @@ template <typename T> int launch_dot(const T* a, const T* b, long n, double* par
 // x[j*N + gidx[p]] = (per_point ? U[dim*p + j] : U[j]) for p < ng, j < dim
 int launch_set_gamma(double* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N,
                      hipStream_t s);
+int launch_set_gamma_f32(float* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N,
+                         hipStream_t s);
 // out[dim*p + j] = x[j*N + gidx[p]]
 int launch_gather_gamma(double* out, const double* x, const int64_t* gidx, long ng, int dim, long N, hipStream_t s);
 
@@ -56,8 +58,9 @@ int launch_predictor(const double* u, const double* v, const double* a, double* 
                      hipStream_t s);
 // Newmark corrector (an = (un - ut)/(beta dt^2); v += dt((1-g) a + g an); a = an) fused
 // with the next predictor (ut = un + dt v + dt^2 (1/2 - beta) a) and b = rho ut.
+// inc (or null): vec_blocks(N ncomp) per-block sums of |ut_new - un|^2.
 int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
-                               const double* rho, long N, int ncomp, double dt, double beta, double gam,
+                               const double* rho, long N, int ncomp, double dt, double beta, double gam, double* inc,
                                hipStream_t s);
 // Initial acceleration from q = A u0: a0 = (rho u0 - q) / (beta dt^2 rho) = div(C : grad^s u0) / rho
 int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* phase, const double* rho, long N,

@@ -280,22 +280,34 @@ template <typename T> int launch_dot(const T* a, const T* b, long n, double* par
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-__global__ void k_set_gamma(double* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N)
+template <typename T>
+__global__ void k_set_gamma(T* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N)
 {
     const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= ng * dim) return;
     const long p = i / dim;
     const int j = (int)(i % dim);
-    x[j * N + gidx[p]] = per_point ? U[i] : U[j];
+    x[j * N + gidx[p]] = (T)(per_point ? U[i] : U[j]);
+}
+template <typename T>
+static int set_gamma_impl(T* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N,
+                          hipStream_t s)
+{
+    if (ng == 0) return 0;
+    const long n = ng * dim;
+    hipLaunchKernelGGL(k_set_gamma<T>, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, gidx, ng,
+                       U, per_point, dim, N);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 int launch_set_gamma(double* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N,
                      hipStream_t s)
 {
-    if (ng == 0) return 0;
-    const long n = ng * dim;
-    hipLaunchKernelGGL(k_set_gamma, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, x, gidx, ng, U,
-                       per_point, dim, N);
-    return hipGetLastError() == hipSuccess ? 0 : -2;
+    return set_gamma_impl<double>(x, gidx, ng, U, per_point, dim, N, s);
+}
+int launch_set_gamma_f32(float* x, const int64_t* gidx, long ng, const double* U, int per_point, int dim, long N,
+                         hipStream_t s)
+{
+    return set_gamma_impl<float>(x, gidx, ng, U, per_point, dim, N, s);
 }
 
 __global__ void k_gather_gamma(double* out, const double* x, const int64_t* gidx, long ng, int dim, long N)
@@ -339,13 +351,16 @@ int launch_predictor(const double* u, const double* v, const double* a, double* 
 // Corrector of this step fused with the predictor of the next one:
 // a_n = (u_n - u~)/(beta dt^2), v_n = v + dt((1 - gamma) a + gamma a_n), then
 // u~' = u_n + dt v_n + dt^2 (1/2 - beta) a_n and b' = rho u~' (ut and b overwritten).
+// inc (or null): per-block sums of |u~' - u_n|^2 (the learned start's scale).
 __global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __restrict__ un, double* __restrict__ ut,
                                                                 double* __restrict__ v, double* __restrict__ a,
                                                                 double* __restrict__ b,
                                                                 const uint16_t* __restrict__ phase,
                                                                 const double* __restrict__ rho, long N, long n,
-                                                                double dt, double inv_bdt2, double gam, double c2)
+                                                                double dt, double inv_bdt2, double gam, double c2,
+                                                                double* __restrict__ inc)
 {
+    double acc = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const double u = un[i];
         const double an = (u - ut[i]) * inv_bdt2;
@@ -355,15 +370,29 @@ __global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __
         const double w = u + dt * vn + c2 * an;
         ut[i] = w;
         b[i] = rho[phase[i % N]] * w;
+        acc += (w - u) * (w - u);
+    }
+    if (inc) {
+        __shared__ double sh[kBlock / 64];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) acc += __shfl_xor(acc, o, 64);
+        if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            double t = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; w++) t += sh[w];
+            inc[blockIdx.x] = t;
+        }
     }
 }
 int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
                                const double* rho, long N, int ncomp, double dt, double beta, double gam,
-                               hipStream_t s)
+                               double* inc, hipStream_t s)
 {
     const long n = N * ncomp;
     hipLaunchKernelGGL(k_corrector_predictor, dim3(vec_blocks(n)), dim3(kBlock), 0, s, un, ut, v, a, b, phase, rho, N,
-                       n, dt, 1.0 / (beta * dt * dt), gam, dt * dt * (0.5 - beta));
+                       n, dt, 1.0 / (beta * dt * dt), gam, dt * dt * (0.5 - beta), inc);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
