@@ -201,6 +201,42 @@ def test_training_lowers_loss_and_learned_start_keeps_the_solution():
     net.close()
 
 
+def test_learned_start_with_mixed_precision_keeps_the_solution():
+    """Learned start under mixed precision: the prediction kernel also writes the FP32 copy
+    the first refinement sweep starts from (with the prescribed Gamma values set in both
+    copies) and the scale comes from the sums the fused corrector left.  The trajectory must
+    agree with the FP64 zero-start one to the mixed-precision tolerance, on the slab and on a
+    sphere source with per-step varying values."""
+    for gamma in ("slab", "sphere"):
+        kw = dict(gamma="sphere", sphere_radius=4.0) if gamma == "sphere" else {}
+        pb = W.make_polycrystal(n=32, n_grains=8, seed=1007, n_steps=10, **kw)
+        net = nmb.Net(seed=3)
+        res = {}
+        for name, prec, ws in (("fp64", nmb.PREC_FP64, nmb.WS_COLD), ("mixed_learned", nmb.PREC_MIXED,
+                                                                        nmb.WS_LEARNED)):
+            opts = nmb.Options(tol=1e-9, max_iter=500, warm_start=ws, precision=prec, inner_tol=1e-5)
+            with nmb.newmark_init_problem(pb, opts) as ctx:
+                if ws == nmb.WS_LEARNED:
+                    nmb.ws_attach(ctx, net)
+                us, st = [], []
+                for s in range(8):
+                    st.append(nmb.newmark_step(ctx, pb.U(s + 1)))
+                    us.append(nmb.get_state(ctx)["u"].reshape(3, -1).copy())
+            res[name] = (us, st)
+        errs = [np.linalg.norm(a - b) / np.linalg.norm(a) for a, b in zip(res["fp64"][0], res["mixed_learned"][0])
+                if np.abs(a).max() > 0]
+        print(f"{gamma}: learned+mixed vs FP64 max rel L2 {max(errs):.2e}, relres "
+              f"{max(x['relres'] for x in res['mixed_learned'][1]):.2e}, sweeps "
+              f"{[x['sweeps'] for x in res['mixed_learned'][1]]}", flush=True)
+        assert max(x["relres"] for x in res["mixed_learned"][1]) <= 1e-9
+        assert max(errs) < 1e-5
+        for s, u in enumerate(res["mixed_learned"][0]):
+            want = pb.U(s + 1)
+            for c in range(3):
+                assert np.array_equal(u[c, pb.gamma_idx], np.full(pb.gamma_idx.size, want[c]))
+        net.close()
+
+
 def test_features_and_target_match_the_newmark_state():
     """Features from (u_n, v_n, a_n), scale s = rms(u~ - u_n) and target (u_{n+1} - u~)/s,
     recomputed in FP64 from the library's own state (the predictor u~ written out from the
