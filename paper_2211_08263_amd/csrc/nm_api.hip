@@ -84,7 +84,7 @@ struct nm_ctx {
     float* matf = nullptr;
     double* wscale = nullptr;
     double* wred = nullptr;
-    float* l0mat = nullptr;
+    uint16_t* l0mat = nullptr; // BF16 [N][16]
     unsigned long long l0mat_version = 0;
 };
 

@@ -26,7 +26,7 @@ struct WarmArgs {
     double* red;           // >= 512 partial sums
     double* scale;         // one double: rms(u~ - u_n)
     uint16_t* feat;        // BF16 [N][32]
-    float* l0mat;          // FP32 [N][16]: material share of layer 0 (with its bias)
+    uint16_t* l0mat;       // BF16 [N][16]: material share of layer 0 (with its bias)
     unsigned long long* l0mat_version; // network version l0mat was computed for (0: none)
     const double* inc = nullptr; // per-block sums of |u~ - u_n|^2 left by the corrector (null: summed here)
     int inc_nb = 0;              // number of those sums

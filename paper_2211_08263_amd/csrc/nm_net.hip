@@ -68,7 +68,8 @@ __device__ __forceinline__ long tap_voxel(int x, int y, int z, int t, const Grid
 // Epilogues: EPI_BF16_ACT  -> BF16 [N][16], leaky ReLU
 //            EPI_F32       -> FP32 [N][ostride] (channels < cout), no activation
 //            EPI_BF16_DACT -> BF16 [N][16] times leaky'(aux), aux BF16 [N][16] (backward data pass)
-//            EPI_BF16_ACT_ADD -> BF16 [N][16], leaky ReLU of the sum with aux, FP32 [N][16]
+//            EPI_BF16_ACT_ADD -> BF16 [N][16], leaky ReLU of the sum with aux, BF16 [N][16]
+//            EPI_BF16      -> BF16 [N][16], no activation
 //
 // A block owns a 16 (x) by TY (y) column of voxels over ZC consecutive z planes.
 // It keeps three halo planes of the input ((TY + 2) x 18 voxels, all CINP
@@ -81,7 +82,7 @@ __device__ __forceinline__ long tap_voxel(int x, int y, int z, int t, const Grid
 // LDS plane layout: [kc][row][col][16 channels] BF16, so the 64 lanes of one
 // A-operand read cover 512 contiguous bytes.
 // ---------------------------------------------------------------------------
-enum { EPI_BF16_ACT = 0, EPI_F32 = 1, EPI_BF16_DACT = 2, EPI_BF16_ACT_ADD = 3 };
+enum { EPI_BF16_ACT = 0, EPI_F32 = 1, EPI_BF16_DACT = 2, EPI_BF16_ACT_ADD = 3, EPI_BF16 = 4 };
 
 constexpr int kTX = 16;            // x extent of a block tile
 constexpr int kHX = kTX + 2;       // halo columns
@@ -228,15 +229,13 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
                 float o[4] = {o4.x, o4.y, o4.z, o4.w};
                 if constexpr (EPI == EPI_BF16_ACT || EPI == EPI_BF16_ACT_ADD) {
                     if constexpr (EPI == EPI_BF16_ACT_ADD) {
-                        const float4 ad = *(const float4*)((const float*)aux + (v0 + vv) * kHid + c0);
-                        o[0] += ad.x;
-                        o[1] += ad.y;
-                        o[2] += ad.z;
-                        o[3] += ad.w;
+                        const uint64_t ap = *(const uint64_t*)((const uint16_t*)aux + (v0 + vv) * kHid + c0);
+#pragma unroll
+                        for (int c = 0; c < 4; c++) o[c] += bf2f((uint16_t)(ap >> (16 * c)));
                     }
 #pragma unroll
                     for (int c = 0; c < 4; c++) o[c] = o[c] > 0.f ? o[c] : kLeak * o[c];
-                } else {
+                } else if constexpr (EPI == EPI_BF16_DACT) {
                     const uint64_t ap = *(const uint64_t*)((const uint16_t*)aux + (v0 + vv) * kHid + c0);
 #pragma unroll
                     for (int c = 0; c < 4; c++) {
@@ -607,6 +606,7 @@ static int launch_conv(int cinp, int epi, const uint16_t* X, const uint16_t* W, 
     else if (cinp == 16 && epi == EPI_F32) NM_CONV_LAUNCH(16, EPI_F32);
     else if (cinp == 16 && epi == EPI_BF16_DACT) NM_CONV_LAUNCH(16, EPI_BF16_DACT);
     else if (cinp == 16 && epi == EPI_BF16_ACT_ADD) NM_CONV_LAUNCH(16, EPI_BF16_ACT_ADD);
+    else if (cinp == 32 && epi == EPI_BF16) NM_CONV_LAUNCH(32, EPI_BF16);
     else return -1;
 #undef NM_CONV_LAUNCH
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -983,8 +983,9 @@ int warm_features(const WarmArgs& a, hipStream_t s)
 
 // Inference inside the solver.  The 22 material channels of the features do not change
 // from step to step, so their share of layer 0 (with its bias) is computed once per
-// network version and problem into l0mat (FP32 [N][16]); each step then convolves only
-// the 9 state channels (16-channel layout) and adds l0mat before the activation.
+// network version and problem into l0mat (BF16 [N][16], the precision of the layer's
+// output); each step then convolves only the 9 state channels (16-channel layout) and
+// adds l0mat before the activation.
 int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
 {
     Grid g{a.n1, a.n2, a.n3, a.N};
@@ -994,7 +995,7 @@ int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
     if (*a.l0mat_version != net->version) {
         hipLaunchKernelGGL(k_features_material, dim3(2048), dim3(256), 0, s, a.phase, a.matf, a.N, a.feat);
         const float* b0 = net->p + net->off[0] + layer_w(net, 0);
-        if (launch_conv(32, EPI_F32, a.feat, net->wf[0], b0, a.l0mat, nullptr, g, 16, 16, s)) return -2;
+        if (launch_conv(32, EPI_BF16, a.feat, net->wf[0], b0, a.l0mat, nullptr, g, 16, 16, s)) return -2;
         *a.l0mat_version = net->version;
     }
     const long n = 3 * a.N;
