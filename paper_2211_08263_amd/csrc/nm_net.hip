@@ -13,6 +13,7 @@
 //   A[row = r][k = 4g + i],  B[k = 4g + i][col = r],  D[row = 4g + i][col = r].
 #include "../../include/newmark.h"
 #include "nm_common.h"
+#include <type_traits>
 #include "nm_net.h"
 
 #include <cmath>
@@ -121,18 +122,22 @@ __device__ __forceinline__ void conv_stash(const u32x4 (&buf)[NCH], uint16_t* ds
     }
 }
 
-// K steps of one output plane: CINP == 32 takes one tap (32 channels) per
-// 16x16x32 MFMA; CINP == 16 takes two taps (16 channels each) per MFMA, lanes
-// 0-31 of the A/B operands holding tap 2s and lanes 32-63 tap 2s + 1 (the 28th
-// tap is padding with zero weights).
+// K steps of one input plane: CINP == 32 takes one in-plane tap (32 channels) per
+// 16x16x32 MFMA; CINP == 16 takes two in-plane taps (16 channels each) per MFMA, lanes
+// 0-31 of the A/B operands holding in-plane tap 2s and lanes 32-63 tap 2s + 1 (the
+// tenth tap is padding with zero weights).
 template <int CINP> struct ConvK {
-    static constexpr int STEPS = CINP == 32 ? 27 : 14;
-    // tap whose channels lane group gq (0..3) supplies at step s
+    static constexpr int STEPS = CINP == 32 ? 9 : 5;
+    // in-plane tap (dy, dx) = (t / 3, t % 3) whose channels lane group gq (0..3) supplies at step s
     static __device__ __forceinline__ int tap(int s, int gq) { return CINP == 32 ? s : 2 * s + (gq >> 1); }
 };
 
+// Input planes stream through LDS one at a time; each A fragment read from a plane
+// feeds the three output planes it reaches (taps dz = 0, 1, 2 of outputs p, p - 1,
+// p - 2 in plane-local indices), whose accumulators rotate over three register slots,
+// so every A fragment is read from LDS once instead of three times.
 template <int CINP, int EPI>
-__global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X, const uint16_t* __restrict__ W,
+__global__ __launch_bounds__(256, CINP == 16 ? 3 : 2) void k_conv_fwd(const uint16_t* __restrict__ X, const uint16_t* __restrict__ W,
                                                   const float* __restrict__ bias, void* __restrict__ Y,
                                                   const void* __restrict__ aux, Grid g, int cout, int ostride,
                                                   int TY, int ZC)
@@ -141,8 +146,8 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
     constexpr int PLANE = KC * kHR * kHX * 16;         // BF16 elements per plane slot
     constexpr int NCH = (kHR * kHX * (CINP / 8) + 255) / 256;
     constexpr int STEPS = ConvK<CINP>::STEPS;
-    __shared__ __align__(16) uint16_t pl[3 * PLANE];
-    __shared__ __align__(16) bf16x8 wl[STEPS * 64];    // [step][lane] B fragments
+    __shared__ __align__(16) uint16_t pl[2 * PLANE];
+    __shared__ __align__(16) bf16x8 wl[3 * STEPS * 64]; // [dz][step][lane] B fragments
     __shared__ __align__(16) float stg[4][256];
 
     const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -150,63 +155,45 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
     const int x0 = blockIdx.x * kTX, y0 = blockIdx.y * TY, z0 = blockIdx.z * ZC;
     const int nchunk = (TY + 2) * kHX * (CINP / 8);
 
-    // B fragment of lane (co, gq) at step s: W[tap][co][ci .. ci + 7] (zero past the last tap)
-    for (int e = tid; e < STEPS * 64; e += 256) {
-        const int l = e % 64, st = e / 64, lg = l >> 4;
+    // B fragment of lane (co, gq) at (dz, step): W[dz 9 + in-plane tap][co][ci .. ci + 7]
+    for (int e = tid; e < 3 * STEPS * 64; e += 256) {
+        const int l = e % 64, st = (e / 64) % STEPS, dz = e / (64 * STEPS), lg = l >> 4;
         const int t = ConvK<CINP>::tap(st, lg);
         const int ci = CINP == 32 ? 8 * lg : 8 * (lg & 1);
         bf16x8 w = {0, 0, 0, 0, 0, 0, 0, 0};
-        if (t < 27) w = *(const bf16x8*)(W + ((long)(t * 16 + (l & 15)) * CINP + ci));
+        if (t < 9) w = *(const bf16x8*)(W + ((long)((dz * 9 + t) * 16 + (l & 15)) * CINP + ci));
         wl[e] = w;
     }
     const float bcol = (bias && r < cout) ? bias[r] : 0.0f;
 
-    // A operand of this lane at step s: its tap's (dz, dy, dx) and channel offset
-    int aoff[STEPS], adz[STEPS];
+    // A operand of this lane at step s: its in-plane tap's (dy, dx) and channel offset
+    int aoff[STEPS];
 #pragma unroll
     for (int st = 0; st < STEPS; st++) {
         int t = ConvK<CINP>::tap(st, gq);
-        t = t < 27 ? t : 26; // padding tap: any finite input, zero weights
-        const int dz = t / 9, dy = (t / 3) % 3, dx = t % 3;
+        t = t < 9 ? t : 8; // padding tap: any finite input, zero weights
+        const int dy = t / 3, dx = t % 3;
         const int kc = CINP == 32 ? (gq >> 1) : 0;
-        adz[st] = dz;
         aoff[st] = ((kc * kHR + dy) * kHX + dx + r) * 16 + 8 * (gq & 1);
     }
+    int rowoff[4];
+#pragma unroll
+    for (int j = 0; j < 4; j++) rowoff[j] = min(wv + 4 * j, TY - 1) * (kHX * 16); // rows past TY: not written
 
-    u32x4 bufA[NCH], bufB[NCH];
-    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0 - 1, nchunk);
-    conv_stash<CINP, NCH>(bufA, pl, nchunk);
-    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0, nchunk);
-    conv_stash<CINP, NCH>(bufA, pl + PLANE, nchunk);
-    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0 + 1, nchunk);
-    conv_stash<CINP, NCH>(bufA, pl + 2 * PLANE, nchunk);
-    if (ZC > 1) conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0 + 2, nchunk);
-    __syncthreads();
-
-    // Output plane k: the plane two ahead (z0 + k + 3) is fetched into one register set
-    // while the plane one ahead (z0 + k + 2, fetched a plane earlier) waits in the other
-    // and replaces the oldest LDS plane after the compute.
-    auto plane = [&](int k, u32x4 (&cur)[NCH], u32x4 (&nxt)[NCH]) {
-        if (k + 2 < ZC) conv_fetch<CINP, NCH>(nxt, X, g, x0, y0, z0 + k + 3, nchunk);
-        const uint16_t* sb[3];
+    constexpr bool AUX = EPI == EPI_BF16_ACT_ADD || EPI == EPI_BF16_DACT;
+    const int vv = lane >> 2, c0 = 4 * (lane & 3); // epilogue: lane owns voxel vv, channels c0 .. c0 + 3
+    // the aux operand of output plane k (4 BF16 per row j), fetched ahead of the epilogue
+    auto aux_fetch = [&](uint64_t (&ap)[4], int k) {
+        const int z = z0 + k;
 #pragma unroll
-        for (int dz = 0; dz < 3; dz++) sb[dz] = pl + ((k + dz) % 3) * PLANE;
-        int rowoff[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) rowoff[j] = min(wv + 4 * j, TY - 1) * (kHX * 16); // rows past TY: not written
-        f32x4 acc[4];
-#pragma unroll
-        for (int j = 0; j < 4; j++) acc[j] = f32x4{0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int st = 0; st < STEPS; st++) {
-            const bf16x8 b = wl[st * 64 + lane];
-            const uint16_t* a0 = (adz[st] == 0 ? sb[0] : adz[st] == 1 ? sb[1] : sb[2]) + aoff[st];
-#pragma unroll
-            for (int j = 0; j < 4; j++) {
-                const bf16x8 a = *(const bf16x8*)(a0 + rowoff[j]);
-                acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, acc[j], 0, 0, 0);
-            }
+        for (int j = 0; j < 4; j++) {
+            const int ty = min(wv + 4 * j, TY - 1);
+            const long v0 = ((long)z * g.n2 + (y0 + ty)) * g.n1 + x0;
+            ap[j] = *(const uint64_t*)((const uint16_t*)aux + (v0 + vv) * kHid + c0);
         }
+    };
+    // output plane k (z0 + k) of this block from accumulator slot acc[k mod 3]
+    auto epilogue = [&](const f32x4 (&ac)[4], int k, const uint64_t (&apre)[4]) {
         const int z = z0 + k;
 #pragma unroll
         for (int j = 0; j < 4; j++) {
@@ -216,27 +203,26 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
             if constexpr (EPI == EPI_F32) {
 #pragma unroll
                 for (int i = 0; i < 4; i++)
-                    if (r < cout) ((float*)Y)[(v0 + 4 * gq + i) * ostride + r] = acc[j][i] + bcol;
+                    if (r < cout) ((float*)Y)[(v0 + 4 * gq + i) * ostride + r] = ac[j][i] + bcol;
             } else {
                 // D (voxel 4 gq + i, channel r) -> staging -> lane L owns voxel L / 4, channels 4 (L % 4) .. + 3
 #pragma unroll
-                for (int i = 0; i < 4; i++) stg[wv][(4 * gq + i) * 16 + r] = acc[j][i] + bcol;
+                for (int i = 0; i < 4; i++) stg[wv][(4 * gq + i) * 16 + r] = ac[j][i] + bcol;
                 __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
                 __builtin_amdgcn_wave_barrier();
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-                const int vv = lane >> 2, c0 = 4 * (lane & 3);
                 const float4 o4 = *(const float4*)&stg[wv][vv * 16 + c0];
                 float o[4] = {o4.x, o4.y, o4.z, o4.w};
                 if constexpr (EPI == EPI_BF16_ACT || EPI == EPI_BF16_ACT_ADD) {
                     if constexpr (EPI == EPI_BF16_ACT_ADD) {
-                        const uint64_t ap = *(const uint64_t*)((const uint16_t*)aux + (v0 + vv) * kHid + c0);
+                        const uint64_t ap = apre[j];
 #pragma unroll
                         for (int c = 0; c < 4; c++) o[c] += bf2f((uint16_t)(ap >> (16 * c)));
                     }
 #pragma unroll
                     for (int c = 0; c < 4; c++) o[c] = o[c] > 0.f ? o[c] : kLeak * o[c];
                 } else if constexpr (EPI == EPI_BF16_DACT) {
-                    const uint64_t ap = *(const uint64_t*)((const uint16_t*)aux + (v0 + vv) * kHid + c0);
+                    const uint64_t ap = apre[j];
 #pragma unroll
                     for (int c = 0; c < 4; c++) {
                         const float av = bf2f((uint16_t)(ap >> (16 * c)));
@@ -251,15 +237,65 @@ __global__ __launch_bounds__(256) void k_conv_fwd(const uint16_t* __restrict__ X
                 __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
             }
         }
-        if (k + 1 < ZC) {
-            __syncthreads(); // every wave is done with the oldest plane
-            conv_stash<CINP, NCH>(cur, pl + (k % 3) * PLANE, nchunk);
-            __syncthreads();
+    };
+
+    f32x4 acc[3][4];
+#pragma unroll
+    for (int q = 0; q < 3; q++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[q][j] = f32x4{0.f, 0.f, 0.f, 0.f};
+
+    // plane-local input index p = 0 .. ZC + 1 is global plane z0 - 1 + p; LDS slot p % 2
+    const int NP = ZC + 2;
+    u32x4 bufA[NCH], bufB[NCH];
+    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0 - 1, nchunk);
+    conv_stash<CINP, NCH>(bufA, pl, nchunk);
+    conv_fetch<CINP, NCH>(bufA, X, g, x0, y0, z0, nchunk);
+
+    // SQ = p mod 3 (accumulator slot of output p); cur holds plane p + 1, nxt receives p + 2
+    auto step = [&](int p, auto SQ, u32x4 (&cur)[NCH], u32x4 (&nxt)[NCH]) {
+        constexpr int q0 = decltype(SQ)::value;       // output p     (dz = 0)
+        constexpr int q1 = (q0 + 2) % 3;              // output p - 1 (dz = 1)
+        constexpr int q2 = (q0 + 1) % 3;              // output p - 2 (dz = 2)
+        __syncthreads(); // plane p is in slot p % 2; every wave is done with plane p - 1
+        if (p + 1 < NP) conv_stash<CINP, NCH>(cur, pl + ((p + 1) & 1) * PLANE, nchunk);
+        if (p + 2 < NP) conv_fetch<CINP, NCH>(nxt, X, g, x0, y0, z0 - 1 + p + 2, nchunk);
+        const uint16_t* sb = pl + (p & 1) * PLANE;
+        const bool o0 = p < ZC, o1 = p >= 1 && p - 1 < ZC, o2 = p >= 2;
+        uint64_t apre[4] = {0, 0, 0, 0};
+        if constexpr (AUX) {
+            if (o2) aux_fetch(apre, p - 2);
+        }
+#pragma unroll
+        for (int st = 0; st < STEPS; st++) {
+            const bf16x8 b0 = wl[(0 * STEPS + st) * 64 + lane];
+            const bf16x8 b1 = wl[(1 * STEPS + st) * 64 + lane];
+            const bf16x8 b2 = wl[(2 * STEPS + st) * 64 + lane];
+#pragma unroll
+            for (int j = 0; j < 4; j++) {
+                const bf16x8 a = *(const bf16x8*)(sb + aoff[st] + rowoff[j]);
+                if (o0) acc[q0][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b0, acc[q0][j], 0, 0, 0);
+                if (o1) acc[q1][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b1, acc[q1][j], 0, 0, 0);
+                if (o2) acc[q2][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b2, acc[q2][j], 0, 0, 0);
+            }
+        }
+        // output p - 2 has all three contributions
+        if (o2) {
+            epilogue(acc[q2], p - 2, apre);
+#pragma unroll
+            for (int j = 0; j < 4; j++) acc[q2][j] = f32x4{0.f, 0.f, 0.f, 0.f};
         }
     };
-    for (int k = 0; k < ZC; k += 2) {
-        plane(k, bufA, bufB);
-        if (k + 1 < ZC) plane(k + 1, bufB, bufA);
+    using S0 = std::integral_constant<int, 0>;
+    using S1 = std::integral_constant<int, 1>;
+    using S2 = std::integral_constant<int, 2>;
+    for (int p = 0; p < NP; p += 6) {
+        step(p, S0{}, bufA, bufB);
+        if (p + 1 < NP) step(p + 1, S1{}, bufB, bufA);
+        if (p + 2 < NP) step(p + 2, S2{}, bufA, bufB);
+        if (p + 3 < NP) step(p + 3, S0{}, bufB, bufA);
+        if (p + 4 < NP) step(p + 4, S1{}, bufA, bufB);
+        if (p + 5 < NP) step(p + 5, S2{}, bufB, bufA);
     }
 }
 
