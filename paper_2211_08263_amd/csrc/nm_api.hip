@@ -72,6 +72,8 @@ struct nm_ctx {
     bool pred_ready = false; // ut and b hold the predictor of the coming step (and winc its scale sums)
     double* winc = nullptr;  // per-block sums of |u~ - u_n|^2 from the fused corrector
     bool d32_is_x = false;   // d32 holds the FP32 copy of the initial iterate (learned start)
+    uint16_t* sfeat = nullptr; // unscaled BF16 state features [N][16] of the learned start
+    bool sfeat_ready = false;  // sfeat was written by the last fused corrector
     double* gbuf = nullptr; // dim * max(ng, 1)
     std::vector<double> G, LU, F_last;
     std::vector<int> piv;
@@ -694,6 +696,7 @@ nm::WarmArgs warm_args(nm_ctx* c)
     a.feat = c->feat;
     a.l0mat = c->l0mat;
     a.l0mat_version = &c->l0mat_version;
+    a.sfeat = c->sfeat;
     return a;
 }
 
@@ -949,6 +952,8 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     // predictor and right-hand side, eq. (Fourier_ND_b) (already formed by the previous
     // step's corrector unless the state or b changed since)
     const bool inc_ok = c->pred_ready;
+    const bool sfeat_ok = c->pred_ready && c->sfeat_ready;
+    c->sfeat_ready = false;
     if (!c->pred_ready)
         LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
     c->pred_ready = false;
@@ -965,8 +970,10 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         if (inc_ok) {
             // the corrector of the previous step already summed |u~ - u_n|^2
             wa.inc = c->winc;
-            wa.inc_nb = vec_blocks(n);
+            wa.inc_nb = corrector_blocks(c->N);
         }
+        wa.sfeat = c->sfeat;
+        wa.sfeat_ready = sfeat_ok;
         if (c->opt.precision == NM_PREC_MIXED) {
             // the first refinement sweep starts from the FP32 copy
             wa.x0f = c->d32;
@@ -1061,8 +1068,11 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     }
     // corrector, fused with the predictor and right-hand side of the next step; then
     // u <- u_n (pointer swap)
+    // with the learned start the corrector also leaves the next step's state features
+    uint16_t* sf = (c->opt.warm_start == NM_WS_LEARNED && c->net && c->sfeat) ? c->sfeat : nullptr;
     LCHK(c, launch_corrector_predictor(c->w, c->ut, c->v, c->a, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta,
-                                       c->gam, c->winc, s));
+                                       c->gam, c->winc, sf, s));
+    c->sfeat_ready = sf != nullptr;
     std::swap(c->u, c->w);
     HIPCHK(c, hipStreamSynchronize(s));
     c->pred_ready = true;
@@ -1178,6 +1188,7 @@ int nm_ws_attach(nm_ctx* c, nm_net* net)
     c->net = net;
     if (!net || c->feat) return NM_OK;
     CHK(dalloc(c, &c->feat, 32 * (size_t)c->N));
+    CHK(dalloc(c, &c->sfeat, 16 * (size_t)c->N));
     CHK(dalloc(c, &c->matf, 22 * (size_t)c->nph));
     CHK(dalloc(c, &c->wscale, 1));
     CHK(dalloc(c, &c->wred, 512));

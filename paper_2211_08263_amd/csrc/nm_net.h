@@ -31,6 +31,8 @@ struct WarmArgs {
     const double* inc = nullptr; // per-block sums of |u~ - u_n|^2 left by the corrector (null: summed here)
     int inc_nb = 0;              // number of those sums
     float* x0f = nullptr;        // warm_predict: FP32 copy of x0 as well (or null)
+    uint16_t* sfeat = nullptr;   // warm_predict: unscaled BF16 state features [N][16]
+    bool sfeat_ready = false;    // sfeat already holds them (written by the fused corrector)
 };
 
 int warm_features(const WarmArgs& a, hipStream_t s);

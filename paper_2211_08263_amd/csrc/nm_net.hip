@@ -85,6 +85,11 @@ __device__ __forceinline__ long tap_voxel(int x, int y, int z, int t, const Grid
 // ---------------------------------------------------------------------------
 enum { EPI_BF16_ACT = 0, EPI_F32 = 1, EPI_BF16_DACT = 2, EPI_BF16_ACT_ADD = 3, EPI_BF16 = 4 };
 
+// EPI_BF16_ACT_ADD with scale set: the convolution output is multiplied by 1/scale[0]
+// (0 if the scale is 0) before aux is added.
+struct ConvExtra {
+    const double* scale = nullptr;
+};
 constexpr int kTX = 16;            // x extent of a block tile
 constexpr int kHX = kTX + 2;       // halo columns
 constexpr int kMaxTY = 16;         // y extent of a block tile (rows of 16 voxels)
@@ -140,7 +145,7 @@ template <int CINP, int EPI>
 __global__ __launch_bounds__(256, CINP == 16 ? 3 : 2) void k_conv_fwd(const uint16_t* __restrict__ X, const uint16_t* __restrict__ W,
                                                   const float* __restrict__ bias, void* __restrict__ Y,
                                                   const void* __restrict__ aux, Grid g, int cout, int ostride,
-                                                  int TY, int ZC)
+                                                  int TY, int ZC, ConvExtra ex)
 {
     constexpr int KC = CINP / 16;
     constexpr int PLANE = KC * kHR * kHX * 16;         // BF16 elements per plane slot
@@ -165,6 +170,10 @@ __global__ __launch_bounds__(256, CINP == 16 ? 3 : 2) void k_conv_fwd(const uint
         wl[e] = w;
     }
     const float bcol = (bias && r < cout) ? bias[r] : 0.0f;
+    float einv = 1.0f; // EPI_BF16_ACT_ADD: 1/s applied to the convolution output
+    if constexpr (EPI == EPI_BF16_ACT_ADD) {
+        if (ex.scale) einv = ex.scale[0] > 0.0 ? (float)(1.0 / ex.scale[0]) : 0.0f;
+    }
 
     // A operand of this lane at step s: its in-plane tap's (dy, dx) and channel offset
     int aoff[STEPS];
@@ -215,6 +224,9 @@ __global__ __launch_bounds__(256, CINP == 16 ? 3 : 2) void k_conv_fwd(const uint
                 float o[4] = {o4.x, o4.y, o4.z, o4.w};
                 if constexpr (EPI == EPI_BF16_ACT || EPI == EPI_BF16_ACT_ADD) {
                     if constexpr (EPI == EPI_BF16_ACT_ADD) {
+                        // unscaled inputs: the convolution is linear, so 1/s applies to its output
+#pragma unroll
+                        for (int c = 0; c < 4; c++) o[c] *= einv;
                         const uint64_t ap = apre[j];
 #pragma unroll
                         for (int c = 0; c < 4; c++) o[c] += bf2f((uint16_t)(ap >> (16 * c)));
@@ -523,7 +535,8 @@ __global__ __launch_bounds__(256) void k_features_state(const double* __restrict
                                                         const double* __restrict__ a, double dt, double c2, long N,
                                                         const double* __restrict__ scale, uint16_t* __restrict__ X)
 {
-    const double inv = scale[0] > 0.0 ? 1.0 / scale[0] : 0.0;
+    // scale null: unscaled features (the solver's first layer applies 1/s itself)
+    const double inv = scale ? (scale[0] > 0.0 ? 1.0 / scale[0] : 0.0) : 1.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < N; i += (long)gridDim.x * blockDim.x) {
         uint16_t f[16];
 #pragma unroll
@@ -627,7 +640,8 @@ __global__ __launch_bounds__(256) void k_dz_soa(const double* __restrict__ g, do
 // Host side
 // ---------------------------------------------------------------------------
 static int launch_conv(int cinp, int epi, const uint16_t* X, const uint16_t* W, const float* bias, void* Y,
-                       const void* aux, const Grid& g, int cout, int ostride, hipStream_t s)
+                       const void* aux, const Grid& g, int cout, int ostride, hipStream_t s,
+                       const ConvExtra& ex = ConvExtra{})
 {
     // tiles: 16 x TY x ZC voxels per block (grid dimensions are powers of two, n1 >= 16)
     const int TY = g.n2 < kMaxTY ? g.n2 : kMaxTY;
@@ -635,7 +649,7 @@ static int launch_conv(int cinp, int epi, const uint16_t* X, const uint16_t* W, 
     const dim3 grid(g.n1 / kTX, g.n2 / TY, g.n3 / ZC);
     if (g.n1 % kTX) return -1;
 #define NM_CONV_LAUNCH(CI, EP)                                                                                         \
-    hipLaunchKernelGGL((k_conv_fwd<CI, EP>), grid, dim3(256), 0, s, X, W, bias, Y, aux, g, cout, ostride, TY, ZC)
+    hipLaunchKernelGGL((k_conv_fwd<CI, EP>), grid, dim3(256), 0, s, X, W, bias, Y, aux, g, cout, ostride, TY, ZC, ex)
     if (cinp == 32 && epi == EPI_BF16_ACT) NM_CONV_LAUNCH(32, EPI_BF16_ACT);
     else if (cinp == 32 && epi == EPI_F32) NM_CONV_LAUNCH(32, EPI_F32);
     else if (cinp == 16 && epi == EPI_BF16_ACT) NM_CONV_LAUNCH(16, EPI_BF16_ACT);
@@ -1027,6 +1041,7 @@ int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
     Grid g{a.n1, a.n2, a.n3, a.N};
     int n3[3] = {a.n1, a.n2, a.n3};
     if (check_grid(n3) != NM_OK) return -1;
+    if (!a.sfeat || !a.l0mat || !a.feat || !a.scale || !a.ut || !x0) return -1;
     if (net_workspace(net, g.N) != NM_OK) return -2;
     if (*a.l0mat_version != net->version) {
         hipLaunchKernelGGL(k_features_material, dim3(2048), dim3(256), 0, s, a.phase, a.matf, a.N, a.feat);
@@ -1041,9 +1056,17 @@ int warm_predict(nm_net* net, const WarmArgs& a, double* x0, hipStream_t s)
         hipLaunchKernelGGL(k_incr_norm, dim3(512), dim3(256), 0, s, a.ut, a.u, n, a.red);
         hipLaunchKernelGGL(k_sum_scale, dim3(1), dim3(64), 0, s, a.red, 512, n, a.scale);
     }
-    hipLaunchKernelGGL(k_features_state, dim3(2048), dim3(256), 0, s, a.u, a.v, a.a, a.dt, a.c2, a.N, a.scale,
-                       a.feat);
-    if (launch_conv(16, EPI_BF16_ACT_ADD, a.feat, net->wf0s, nullptr, net->act[1], a.l0mat, g, 16, 16, s)) return -2;
+    // unscaled state features (left by the corrector of the previous step unless the state
+    // changed since); layer 0 applies 1/s to its state share
+    if (!a.sfeat_ready)
+        hipLaunchKernelGGL(k_features_state, dim3(2048), dim3(256), 0, s, a.u, a.v, a.a, a.dt, a.c2, a.N, nullptr,
+                           a.sfeat);
+    {
+        ConvExtra ex;
+        ex.scale = a.scale;
+        if (launch_conv(16, EPI_BF16_ACT_ADD, a.sfeat, net->wf0s, nullptr, net->act[1], a.l0mat, g, 16, 16, s, ex))
+            return -2;
+    }
     for (int l = 1; l < net->L; l++) {
         const float* b = net->p + net->off[l] + layer_w(net, l);
         int e;

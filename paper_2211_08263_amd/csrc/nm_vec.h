@@ -58,10 +58,12 @@ int launch_predictor(const double* u, const double* v, const double* a, double* 
                      hipStream_t s);
 // Newmark corrector (an = (un - ut)/(beta dt^2); v += dt((1-g) a + g an); a = an) fused
 // with the next predictor (ut = un + dt v + dt^2 (1/2 - beta) a) and b = rho ut.
-// inc (or null): vec_blocks(N ncomp) per-block sums of |ut_new - un|^2.
+// inc (or null): corrector_blocks(N) per-block sums of |ut_new - un|^2; feat (or null):
+// unscaled BF16 state features [N][16] of the new state (u, dt v, dt^2 (1/2 - beta) a).
+int corrector_blocks(long N);
 int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
                                const double* rho, long N, int ncomp, double dt, double beta, double gam, double* inc,
-                               hipStream_t s);
+                               uint16_t* feat, hipStream_t s);
 // Initial acceleration from q = A u0: a0 = (rho u0 - q) / (beta dt^2 rho) = div(C : grad^s u0) / rho
 int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* phase, const double* rho, long N,
                   int ncomp, double bdt2, hipStream_t s);

@@ -348,29 +348,60 @@ int launch_predictor(const double* u, const double* v, const double* a, double* 
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+// BF16 (round to nearest even) of a float, for the feature output of the corrector.
+__device__ __forceinline__ uint16_t bf16_rne(float f)
+{
+    uint32_t x = __float_as_uint(f);
+    if ((x & 0x7f800000u) == 0x7f800000u) return (uint16_t)(x >> 16); // inf / nan
+    x += 0x7fffu + ((x >> 16) & 1u);
+    return (uint16_t)(x >> 16);
+}
+
 // Corrector of this step fused with the predictor of the next one:
 // a_n = (u_n - u~)/(beta dt^2), v_n = v + dt((1 - gamma) a + gamma a_n), then
 // u~' = u_n + dt v_n + dt^2 (1/2 - beta) a_n and b' = rho u~' (ut and b overwritten).
 // inc (or null): per-block sums of |u~' - u_n|^2 (the learned start's scale).
+// feat (or null): the learned start's state features of the new state, unscaled, BF16
+// [N][16]: (u_n, dt v_n, dt^2 (1/2 - beta) a_n) per component, channels 9..15 zero.
+// One thread per voxel and its three components.
 __global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __restrict__ un, double* __restrict__ ut,
                                                                 double* __restrict__ v, double* __restrict__ a,
                                                                 double* __restrict__ b,
                                                                 const uint16_t* __restrict__ phase,
-                                                                const double* __restrict__ rho, long N, long n,
+                                                                const double* __restrict__ rho, long N,
                                                                 double dt, double inv_bdt2, double gam, double c2,
-                                                                double* __restrict__ inc)
+                                                                double* __restrict__ inc, uint16_t* __restrict__ feat)
 {
     double acc = 0.0;
-    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
-        const double u = un[i];
-        const double an = (u - ut[i]) * inv_bdt2;
-        const double vn = v[i] + dt * ((1.0 - gam) * a[i] + gam * an);
-        v[i] = vn;
-        a[i] = an;
-        const double w = u + dt * vn + c2 * an;
-        ut[i] = w;
-        b[i] = rho[phase[i % N]] * w;
-        acc += (w - u) * (w - u);
+    for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (long)gridDim.x * blockDim.x) {
+        const double rp = rho[phase[p]];
+        uint16_t f[16];
+#pragma unroll
+        for (int k = 0; k < 16; k++) f[k] = 0;
+#pragma unroll
+        for (int c = 0; c < 3; c++) {
+            const long i = c * N + p;
+            const double u = un[i];
+            const double an = (u - ut[i]) * inv_bdt2;
+            const double vn = v[i] + dt * ((1.0 - gam) * a[i] + gam * an);
+            v[i] = vn;
+            a[i] = an;
+            const double w = u + dt * vn + c2 * an;
+            ut[i] = w;
+            b[i] = rp * w;
+            acc += (w - u) * (w - u);
+            f[c] = bf16_rne((float)u);
+            f[3 + c] = bf16_rne((float)(dt * vn));
+            f[6 + c] = bf16_rne((float)(c2 * an));
+        }
+        if (feat) {
+#pragma unroll
+            for (int k = 0; k < 16; k += 4) {
+                const uint64_t wv = (uint64_t)f[k] | ((uint64_t)f[k + 1] << 16) | ((uint64_t)f[k + 2] << 32) |
+                                    ((uint64_t)f[k + 3] << 48);
+                *(uint64_t*)(feat + p * 16 + k) = wv;
+            }
+        }
     }
     if (inc) {
         __shared__ double sh[kBlock / 64];
@@ -386,13 +417,14 @@ __global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __
         }
     }
 }
+int corrector_blocks(long N) { return vec_blocks(N); }
 int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
                                const double* rho, long N, int ncomp, double dt, double beta, double gam,
-                               double* inc, hipStream_t s)
+                               double* inc, uint16_t* feat, hipStream_t s)
 {
-    const long n = N * ncomp;
-    hipLaunchKernelGGL(k_corrector_predictor, dim3(vec_blocks(n)), dim3(kBlock), 0, s, un, ut, v, a, b, phase, rho, N,
-                       n, dt, 1.0 / (beta * dt * dt), gam, dt * dt * (0.5 - beta), inc);
+    if (ncomp != 3) return -1;
+    hipLaunchKernelGGL(k_corrector_predictor, dim3(corrector_blocks(N)), dim3(kBlock), 0, s, un, ut, v, a, b, phase,
+                       rho, N, dt, 1.0 / (beta * dt * dt), gam, dt * dt * (0.5 - beta), inc, feat);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
