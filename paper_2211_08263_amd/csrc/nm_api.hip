@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 using namespace nm;
@@ -285,7 +286,8 @@ struct PcgResult {
 // between the preconditioner's z pass and the next direction update.
 template <typename T>
 int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* p, T* q, bool masked, bool x_zero, double bref, double tol,
-        int max_iter, int fixed_iters, bool allow_unconverged, PcgResult* res, double rr_known = -1.0)
+        int max_iter, int fixed_iters, bool allow_unconverged, PcgResult* res, double rr_known = -1.0,
+        double* x64 = nullptr)
 {
     hipStream_t s = c->stream;
     const uint8_t* mk = masked ? c->mask : nullptr;
@@ -374,8 +376,14 @@ int pcg(nm_ctx* c, const T* rhs, T* x, T* r, T* p, T* q, bool masked, bool x_zer
         res->rr = rr;
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual at iteration %d", it);
         if (c->hscal[S_STOP] != 0.0) {
-            // the last iteration's x += alpha p
-            LCHK(c, launch_axpy_scal<T>(x, p, c->scal + S_ALPHA, n, s));
+            // the last iteration's x += alpha p (FP32 with x64: folded into x64 += x + alpha p,
+            // x itself left without it)
+            if constexpr (std::is_same<T, float>::value) {
+                if (x64) LCHK(c, launch_add_f2d_axpy(x64, x, p, c->scal + S_ALPHA, n, s));
+                else LCHK(c, launch_axpy_scal<T>(x, p, c->scal + S_ALPHA, n, s));
+            } else {
+                LCHK(c, launch_axpy_scal<T>(x, p, c->scal + S_ALPHA, n, s));
+            }
             if (fixed || rr <= thr2) break;
             if (allow_unconverged) return NM_OK;
             return fail(c, NM_ENOTCONV, "PCG did not reach tol %.3g in %d iterations (rel %.3g)", tol, max_iter,
@@ -411,7 +419,7 @@ int projected_bref(nm_ctx* c, const double* x, double* bref)
         LCHK(c, launch_set_gamma(c->z, c->gidx, c->ng, c->gbuf, 1, 3, c->N, s));
     }
     CHK(apply_A<double>(c, c->z, c->q, c->mask));
-    LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+    LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s, c->r32));
     LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
     CHK(read_scalars(c));
     *bref = std::sqrt(c->hscal[S_RR]);
@@ -423,7 +431,7 @@ int projected_bref(nm_ctx* c, const double* x, double* bref)
 int lift_bref(nm_ctx* c, const double* U3, double* bref)
 {
     hipStream_t s = c->stream;
-    LCHK(c, launch_lift_residual(c->b, c->lift, U3, c->mask, c->N, c->r, c->part_a, s));
+    LCHK(c, launch_lift_residual(c->b, c->lift, U3, c->mask, c->N, c->r, c->part_a, s, c->r32));
     LCHK(c, launch_reduce(c->part_a, vec_blocks(3 * c->N), c->scal, RED_STORE_RR, 0, s));
     CHK(read_scalars(c));
     *bref = std::sqrt(c->hscal[S_RR]);
@@ -453,7 +461,7 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
             // tol b_ref, so its FP32 rounding (a few 1e-7 of |A d|) stays below 1e-2 tol b_ref
             // and the stopping test still certifies the FP64 iterate
             CHK(apply_A<float>(c, c->d32, c->q32, c->mask));
-            LCHK(c, launch_update_f32q(c->r, c->q32, c->mask, c->N, c->part_a, s));
+            LCHK(c, launch_update_f32q(c->r, c->q32, c->mask, c->N, c->part_a, s, c->r32));
             LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
             CHK(read_scalars(c));
             rr = c->hscal[S_RR];
@@ -464,14 +472,14 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
             if (!c->d32_is_x) LCHK(c, launch_cast_d2f(c->d32, x, n, s));
             c->d32_is_x = false;
             CHK(apply_A<float>(c, c->d32, c->q32, c->mask));
-            LCHK(c, launch_residual_f32q(c->b, c->q32, c->r, c->mask, c->N, c->part_a, s));
+            LCHK(c, launch_residual_f32q(c->b, c->q32, c->r, c->mask, c->N, c->part_a, s, c->r32));
             LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
             CHK(read_scalars(c));
             rr = c->hscal[S_RR];
             approx = true;
         } else {
             CHK(apply_A<double>(c, x, c->q, c->mask));
-            LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+            LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s, c->r32));
             LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
             CHK(read_scalars(c));
             rr = c->hscal[S_RR];
@@ -484,17 +492,19 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
                         sweeps, std::sqrt(rr) / bref);
         small_update = !approx && std::sqrt(rr) <= kSmallUpdate * c->opt.tol * bref;
         // the correction starts at zero, so its residual is r itself (already P-projected):
-        // the FP32 solve starts from the rounded copy with the FP64 r.r
-        LCHK(c, launch_cast_d2f(c->r32, c->r, n, s));
+        // the FP32 solve starts from its rounded copy, which every residual kernel of this
+        // path writes beside r, with the FP64 r.r
         LCHK(c, launch_fill<float>(c->d32, 0.0f, n, s));
         PcgResult pr;
         // reduce the residual only as far as the outer tolerance still needs (half of the
         // remaining factor), but never ask FP32 for more than inner_tol
         const double need = 0.5 * c->opt.tol * bref / std::sqrt(rr);
+        // x += d; the correction itself is kept only where the next residual is an FP32 update
         CHK(pcg<float>(c, nullptr, c->d32, c->r32, c->p32, c->q32, true, true, std::sqrt(rr),
-                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr, rr));
+                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr, rr,
+                       small_update ? nullptr : x));
         inner += pr.iters;
-        LCHK(c, launch_add_f2d(x, c->d32, n, s));
+        if (small_update) LCHK(c, launch_add_f2d(x, c->d32, n, s));
         sweeps++;
     }
     if (st) {

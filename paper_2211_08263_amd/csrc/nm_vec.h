@@ -24,22 +24,25 @@ int vec_blocks(long n);
 // r = b - q (masked entries -> 0), partial sums of r.r.
 template <typename T>
 int launch_residual(const T* b, const T* q, T* r, const uint8_t* mask, long N, int ncomp, double* partials,
-                    hipStream_t s);
+                    hipStream_t s, float* r32 = nullptr);
 // out = a + c * b.
 template <typename T> int launch_axpby(T* out, const T* a, const T* b, double c, long n, hipStream_t s);
 // y (FP32) = (float) x (FP64);  x64 += (double) d32
 int launch_cast_d2f(float* y, const double* x, long n, hipStream_t s);
 int launch_add_f2d(double* x, const float* d, long n, hipStream_t s);
+// x += (double)(d + alpha[0] p): the last PCG update of an FP32 correction d folded into x.
+int launch_add_f2d_axpy(double* x, const float* d, const float* p, const double* alpha, long n, hipStream_t s);
 template <typename T> int launch_fill(T* x, T v, long n, hipStream_t s);
 // r = P (b - q) for an FP32 q (FP64 arithmetic), partial sums of r.r.
 int launch_residual_f32q(const double* b, const float* q, double* r, const uint8_t* mask, long N, double* partials,
-                         hipStream_t s);
+                         hipStream_t s, float* r32 = nullptr);
 // r <- P (r - q) in place for an FP32 q (FP64 arithmetic), partial sums of r.r.
-int launch_update_f32q(double* r, const float* q, const uint8_t* mask, long N, double* partials, hipStream_t s);
+int launch_update_f32q(double* r, const float* q, const uint8_t* mask, long N, double* partials, hipStream_t s,
+                       float* r32 = nullptr);
 // r = P (b - sum_c U3[c] G_c) with the three Gamma lifting responses G (3 x (3 x N)),
 // partial sums of r.r (vec_blocks(3 N) of them).
 int launch_lift_residual(const double* b, const double* G, const double* U3, const uint8_t* mask, long N, double* r,
-                         double* partials, hipStream_t s);
+                         double* partials, hipStream_t s, float* r32 = nullptr);
 template <typename T> int launch_copy(T* dst, const T* src, long n, hipStream_t s);
 // partial sums of a.b (FP64 accumulation)
 template <typename T> int launch_dot(const T* a, const T* b, long n, double* partials, hipStream_t s);

@@ -113,13 +113,14 @@ int launch_reduce(const double* partials, int n, double* scal, int action, int s
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ b, const T* __restrict__ q, T* __restrict__ r,
                                                      const uint8_t* __restrict__ mask, long N, long n,
-                                                     double* partials)
+                                                     double* partials, float* __restrict__ r32)
 {
     double acc = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         T v = b[i] - q[i];
         if (mask && mask[i % N]) v = 0;
         r[i] = v;
+        if (r32) r32[i] = (float)v;
         acc += (double)v * (double)v;
     }
     const double s = block_sum_v(acc);
@@ -128,55 +129,58 @@ __global__ __launch_bounds__(kBlock) void k_residual(const T* __restrict__ b, co
 
 template <typename T>
 int launch_residual(const T* b, const T* q, T* r, const uint8_t* mask, long N, int ncomp, double* partials,
-                    hipStream_t s)
+                    hipStream_t s, float* r32)
 {
     const long n = N * ncomp;
-    hipLaunchKernelGGL((k_residual<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, q, r, mask, N, n, partials);
+    hipLaunchKernelGGL((k_residual<T>), dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, q, r, mask, N, n, partials, r32);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // r = P (b - q) with an FP32 q, accumulated in FP64; partial sums of r.r.
 __global__ __launch_bounds__(kBlock) void k_residual_f32q(const double* __restrict__ b, const float* __restrict__ q,
                                                           double* __restrict__ r, const uint8_t* __restrict__ mask,
-                                                          long N, long n, double* partials)
+                                                          long N, long n, double* partials, float* __restrict__ r32)
 {
     double acc = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         double v = b[i] - (double)q[i];
         if (mask && mask[i % N]) v = 0;
         r[i] = v;
+        if (r32) r32[i] = (float)v;
         acc += v * v;
     }
     const double s = block_sum_v(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 int launch_residual_f32q(const double* b, const float* q, double* r, const uint8_t* mask, long N, double* partials,
-                         hipStream_t s)
+                         hipStream_t s, float* r32)
 {
     const long n = 3 * N;
-    hipLaunchKernelGGL(k_residual_f32q, dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, q, r, mask, N, n, partials);
+    hipLaunchKernelGGL(k_residual_f32q, dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, q, r, mask, N, n, partials, r32);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
 // r <- P (r - q) in place for an FP32 q (FP64 arithmetic); partial sums of r.r.
 __global__ __launch_bounds__(kBlock) void k_update_f32q(double* r, const float* __restrict__ q,
                                                         const uint8_t* __restrict__ mask, long N, long n,
-                                                        double* partials)
+                                                        double* partials, float* __restrict__ r32)
 {
     double acc = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         double v = r[i] - (double)q[i];
         if (mask && mask[i % N]) v = 0;
         r[i] = v;
+        if (r32) r32[i] = (float)v;
         acc += v * v;
     }
     const double s = block_sum_v(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
-int launch_update_f32q(double* r, const float* q, const uint8_t* mask, long N, double* partials, hipStream_t s)
+int launch_update_f32q(double* r, const float* q, const uint8_t* mask, long N, double* partials, hipStream_t s,
+                       float* r32)
 {
     const long n = 3 * N;
-    hipLaunchKernelGGL(k_update_f32q, dim3(vec_blocks(n)), dim3(kBlock), 0, s, r, q, mask, N, n, partials);
+    hipLaunchKernelGGL(k_update_f32q, dim3(vec_blocks(n)), dim3(kBlock), 0, s, r, q, mask, N, n, partials, r32);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -185,7 +189,8 @@ int launch_update_f32q(double* r, const float* q, const uint8_t* mask, long N, d
 __global__ __launch_bounds__(kBlock) void k_lift_residual(const double* __restrict__ b, const double* __restrict__ G,
                                                           double U0, double U1, double U2,
                                                           const uint8_t* __restrict__ mask, long N, long n,
-                                                          double* __restrict__ r, double* partials)
+                                                          double* __restrict__ r, double* partials,
+                                                          float* __restrict__ r32)
 {
     double acc = 0.0;
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
@@ -196,17 +201,18 @@ __global__ __launch_bounds__(kBlock) void k_lift_residual(const double* __restri
         double v = b[i] - q;
         if (mask[i % N]) v = 0;
         r[i] = v;
+        if (r32) r32[i] = (float)v;
         acc += v * v;
     }
     const double s = block_sum_v(acc);
     if (threadIdx.x == 0) partials[blockIdx.x] = s;
 }
 int launch_lift_residual(const double* b, const double* G, const double* U3, const uint8_t* mask, long N, double* r,
-                         double* partials, hipStream_t s)
+                         double* partials, hipStream_t s, float* r32)
 {
     const long n = 3 * N;
     hipLaunchKernelGGL(k_lift_residual, dim3(vec_blocks(n)), dim3(kBlock), 0, s, b, G, U3[0], U3[1], U3[2], mask, N, n,
-                       r, partials);
+                       r, partials, r32);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -241,6 +247,23 @@ __global__ __launch_bounds__(kBlock) void k_add_f2d(double* x, const float* d, l
 int launch_add_f2d(double* x, const float* d, long n, hipStream_t s)
 {
     hipLaunchKernelGGL(k_add_f2d, dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, d, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+// x += (double)(d + alpha p) with the FP32 sum rounded as the separate update would round it
+__global__ __launch_bounds__(kBlock) void k_add_f2d_axpy(double* x, const float* __restrict__ d,
+                                                         const float* __restrict__ p, const double* __restrict__ alpha,
+                                                         long n)
+{
+    const float a = (float)alpha[0];
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const float di = d[i] + a * p[i];
+        x[i] += (double)di;
+    }
+}
+int launch_add_f2d_axpy(double* x, const float* d, const float* p, const double* alpha, long n, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_add_f2d_axpy, dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, d, p, alpha, n);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -459,9 +482,9 @@ int launch_taylor(double* x, const double* u, const double* v, const double* a, 
 }
 
 template int launch_residual<double>(const double*, const double*, double*, const uint8_t*, long, int, double*,
-                                     hipStream_t);
+                                     hipStream_t, float*);
 template int launch_residual<float>(const float*, const float*, float*, const uint8_t*, long, int, double*,
-                                    hipStream_t);
+                                    hipStream_t, float*);
 template int launch_axpby<double>(double*, const double*, const double*, double, long, hipStream_t);
 template int launch_axpby<float>(float*, const float*, const float*, double, long, hipStream_t);
 template int launch_fill<double>(double*, double, long, hipStream_t);
