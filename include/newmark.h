@@ -95,7 +95,7 @@ typedef struct nm_step_stats {
     double relres;            /* final relative residual (true residual when measured, else recursive) */
     double relres0;           /* relative residual of the initial guess (first solve) */
     double t_step_ms;         /* wall time of the step (host clock, after a stream synchronize) */
-    double t_warm_ms;         /* wall time of the warm-start prediction */
+    double t_warm_ms;         /* device time of the warm-start prediction (events on the stream) */
 } nm_step_stats;
 
 typedef struct nm_ctx nm_ctx;
