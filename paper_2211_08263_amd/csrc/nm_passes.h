@@ -38,8 +38,9 @@ struct SpecLayout {
 };
 
 // Fused stage in front of the x-direction real-to-complex transform.
-// XF_PUPDATE: p = z + beta p (and the deferred x += alpha p_old); XF_UPDATE: r -= alpha q.
-enum XFwdMode { XF_PLAIN = 0, XF_PUPDATE = 1, XF_UPDATE = 2 };
+// XF_UPDATE: r -= alpha q with the partial sums of r.r (the direction update is fused into
+// the preconditioner's last pass instead, launch_xpupdate).
+enum XFwdMode { XF_PLAIN = 0, XF_UPDATE = 2 };
 // Fused stage after the x-direction complex-to-real transform.
 enum XInvMode { XI_PLAIN = 0, XI_OPERATOR = 1, XI_PRECOND = 2 };
 // Axis-wise derivative stages of the operator on x-spectral (kx, y, z) data:
@@ -60,9 +61,7 @@ enum ScalarSlot {
 };
 
 struct XFwdArgs {
-    const void* src;      // XF_PLAIN: input field; XF_PUPDATE: z
-    void* p;              // XF_PUPDATE: p (in/out)
-    void* x;              // XF_PUPDATE: x (in/out; x += alpha p_old after the first iteration)
+    const void* src;      // XF_PLAIN: input field
     void* r;              // XF_UPDATE: r (in/out)
     const void* q;        // XF_UPDATE: q (in)
     const double* scal;   // device scalars

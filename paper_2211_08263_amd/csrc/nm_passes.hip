@@ -18,7 +18,9 @@
 //   x-inv, sigma = C : eps, x-fwd (6) | y: D_y and i xi1 terms of div (5 -> 3) |
 //   z: D_z terms, -beta dt^2 scale (6 -> 3) | x-inv + rho p (3).
 // The preconditioner z = M r is x-fwd | y-fwd | z-fwd, (beta dt^2 K + rhobar I)^-1,
-// z-inv | y-inv | x-inv (3 components throughout).
+// z-inv | y-inv | x-inv (3 components throughout).  Inside PCG its x-inv is fused with
+// the direction update and the x-fwd of the next operator apply (k_xpupdate), and the
+// residual update r -= alpha q rides on the preconditioner's x-fwd (XF_UPDATE).
 #include "nm_common.h"
 #include "nm_fft.h"
 #include "nm_passes.h"
@@ -135,30 +137,6 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
             const V* src = (const V*)a.src + off;
 #pragma unroll
             for (int m = 0; m < R; m++) v[m] = src[t + m * G];
-        } else if constexpr (MODE == XF_PUPDATE) {
-            // p = z + beta p, and the previous iteration's x += alpha p (deferred to here,
-            // where the old p is read anyway; the caller applies the last one)
-            const V* z = (const V*)a.src + off;
-            V* p = (V*)a.p + off;
-            V* x = (V*)a.x + off;
-            const T beta = (T)a.scal[S_BETA];
-            const T alpha = (T)a.scal[S_ALPHA];
-            const bool first = a.scal[S_FIRST] != 0.0;
-#pragma unroll
-            for (int m = 0; m < R; m++) {
-                const int i = t + m * G;
-                V zz = z[i];
-                V pp = zz;
-                if (!first) {
-                    const V po = p[i];
-                    V xx = x[i];
-                    xx = V{xx.x + alpha * po.x, xx.y + alpha * po.y};
-                    x[i] = xx;
-                    pp = V{zz.x + beta * po.x, zz.y + beta * po.y};
-                }
-                p[i] = pp;
-                v[m] = pp;
-            }
         } else {
             // r -= alpha q and the partial sums of r.r
             const T alpha = (T)a.scal[S_ALPHA];
@@ -980,8 +958,6 @@ template <typename T> int launch_xfwd(int mode, int n1, const XFwdArgs& a, const
     NM_SIZE_SWITCH(n1, {
         constexpr int M = NN / 2, R = (M >= 8 ? 8 : M);
         if (mode == XF_PLAIN) hipLaunchKernelGGL((k_xfwd<T, NN, R, XF_PLAIN>), dim3(blocks), dim3(kBlock), 0, s, a, t);
-        else if (mode == XF_PUPDATE)
-            hipLaunchKernelGGL((k_xfwd<T, NN, R, XF_PUPDATE>), dim3(blocks), dim3(kBlock), 0, s, a, t);
         else hipLaunchKernelGGL((k_xfwd<T, NN, R, XF_UPDATE>), dim3(blocks), dim3(kBlock), 0, s, a, t);
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;
