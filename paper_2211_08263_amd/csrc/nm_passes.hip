@@ -30,9 +30,13 @@
 #ifndef NM_STRESS_PF64
 #define NM_STRESS_PF64 2
 #endif
-// The stress pass keeps its twiddles in registers across its twelve transforms.
-#ifndef NM_STRESS_TWREG
-#define NM_STRESS_TWREG 1
+// The stress pass keeps its twiddles in registers across its twelve transforms (measured:
+// 6% faster in FP64, 5% slower in FP32, where the registers cost occupancy).
+#ifndef NM_STRESS_TWREG64
+#define NM_STRESS_TWREG64 1
+#endif
+#ifndef NM_STRESS_TWREG32
+#define NM_STRESS_TWREG32 0
 #endif
 // Column passes address their tiles as a uniform base plus 32-bit lane offsets.
 #ifndef NM_COL_OFF32
@@ -378,23 +382,29 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
     const int tid = threadIdx.x, ll = tid / G, t = tid % G;
     const long line = (long)blockIdx.x * LPB + ll;
     const bool valid = line < (long)lay.n2 * lay.n3;
-#if NM_STRESS_TWREG
-    // the twelve transforms share their twiddles: read them once into registers
-    TwRegs<M, R, V> twr;
-    twr.load(t, twM);
-    V twn[R];
-#pragma unroll
-    for (int m = 0; m < R; m++) twn[m] = twN[t + m * G];
-#define NM_FFT group_fft_tw
-#define NM_TWM twr
-#define NM_TWN(m, k) twn[m]
-#else
-#define NM_FFT group_fft
-#define NM_TWM twM
-#define NM_TWN(m, k) twN[k]
-#endif
-    const long off = lay.line(line), NS = lay.cs;
     LineAddr<R, (int)sizeof(V)> addr{ll * LP};
+    // the twelve transforms share their twiddles: with TWR they are read once into registers
+    constexpr bool TWR = sizeof(T) == 8 ? NM_STRESS_TWREG64 : NM_STRESS_TWREG32;
+    TwRegs<M, R, V> twr;
+    V twn[R];
+    if constexpr (TWR) {
+        twr.load(t, twM);
+#pragma unroll
+        for (int m = 0; m < R; m++) twn[m] = twN[t + m * G];
+    }
+    auto fft_inv = [&](V (&x)[R]) {
+        if constexpr (TWR) group_fft_tw<M, R, +1, true>(x, t, lds, addr, twr);
+        else group_fft<M, R, +1, true>(x, t, lds, addr, twM);
+    };
+    auto fft_fwd = [&](V (&x)[R]) {
+        if constexpr (TWR) group_fft_tw<M, R, -1, true>(x, t, lds, addr, twr);
+        else group_fft<M, R, -1, true>(x, t, lds, addr, twM);
+    };
+    auto twk = [&](int m, int k) -> V {
+        if constexpr (TWR) return twn[m];
+        else return twN[k];
+    };
+    const long off = lay.line(line), NS = lay.cs;
     // keep the global loads of the next PF strain components in flight while a
     // component is transformed: the fences of the LDS exchanges would otherwise hold
     // each component's loads back until the previous transform is done
@@ -427,10 +437,10 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int k = t + m * G;
-            v[m] = c2r_pre(k, v[m], lds[addr((M - k) & (M - 1))], NM_TWN(m, k));
+            v[m] = c2r_pre(k, v[m], lds[addr((M - k) & (M - 1))], twk(m, k));
         }
         group_sync<true>();
-        NM_FFT<M, R, +1, true>(v, t, lds, addr, NM_TWM);
+        fft_inv(v);
 #pragma unroll
         for (int m = 0; m < R; m++) {
             e[c][2 * m] = v[m].x;
@@ -458,7 +468,7 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
         V v[R];
 #pragma unroll
         for (int m = 0; m < R; m++) v[m] = V{e[c][2 * m], e[c][2 * m + 1]};
-        NM_FFT<M, R, -1, true>(v, t, lds, addr, NM_TWM);
+        fft_fwd(v);
 #pragma unroll
         for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
         group_sync<true>();
@@ -470,14 +480,11 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
 #pragma unroll
             for (int m = 0; m < R; m++) {
                 const int k = t + m * G;
-                spec[c * NS + off + k] = r2c_post(k, v[m], mir[m], NM_TWN(m, k));
+                spec[c * NS + off + k] = r2c_post(k, v[m], mir[m], twk(m, k));
             }
         }
     }
 }
-#undef NM_FFT
-#undef NM_TWM
-#undef NM_TWN
 
 // ---------------------------------------------------------------------------
 // y and z directions: tiles of TX consecutive kx columns, L points each.
