@@ -653,16 +653,24 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
         u[2][m] = z2;
     }
     if (partials) {
-        __shared__ double red[BLK / 64 > 0 ? BLK / 64 : 1];
-        double pd = (kx == 0 ? 1.0 : 2.0) * (double)part;
-        pd = wave_sum(pd);
-        if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = pd;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double tot = 0.0;
-            for (int w = 0; w < (int)((blockDim.x + 63) / 64); w++) tot += red[w];
-            partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        const double pd = (kx == 0 ? 1.0 : 2.0) * (double)part;
+        double tot = 0.0;
+        if (blockDim.x >= 64) {
+            __shared__ double red[BLK / 64 > 0 ? BLK / 64 : 1];
+            const double w = wave_sum(pd);
+            if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = w;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int i = 0; i < (int)(blockDim.x / 64); i++) tot += red[i];
+        } else {
+            // a block narrower than a wavefront (small 2D grids): no cross-lane shuffles
+            __shared__ double red1[64];
+            red1[threadIdx.x] = pd;
+            __syncthreads();
+            if (threadIdx.x == 0)
+                for (int i = 0; i < (int)blockDim.x; i++) tot += red1[i];
         }
+        if (threadIdx.x == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
     }
 #pragma unroll
     for (int j = 0; j < 3; j++) {
