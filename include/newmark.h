@@ -85,7 +85,8 @@ typedef struct nm_options {
     int warm_start;           /* nm_warm_start */
     double green_tol;         /* tolerance of the unit-force solves that build G */
     int compute_reaction;     /* projected route: also compute F on Gamma (one extra operator apply) */
-    int true_residual;        /* FP64 route: report ||P(b - A u)|| / ||b_ref|| (one extra operator apply) */
+    int true_residual;        /* projected route: report the FP64 ||P(b - A u)|| / ||b_ref|| of the solution
+                                 (one extra FP64 operator apply) instead of the solver's own estimate */
 } nm_options;
 
 typedef struct nm_step_stats {

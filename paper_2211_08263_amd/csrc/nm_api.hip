@@ -453,10 +453,19 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
     int sweeps = 0, inner = 0;
     double rr = 0;
     bool small_update = false; // the last correction is small enough for an FP32 residual update
+    PcgResult pr;              // the last correction solve
     for (;;) {
         bool approx = false;
         if (sweeps == 0 && rr_known >= 0) {
             rr = rr_known;
+        } else if (small_update && pr.converged && pr.rr <= 0.25 * c->opt.tol * c->opt.tol * bref * bref) {
+            // the correction solve's recursively updated residual r - P A d (FP32 operator,
+            // FP32 updates) stands for the new residual: |r| <= kSmallUpdate tol b_ref, so
+            // the operator's FP32 rounding and the updates' (together a few 1e-7 of |r| per
+            // iteration) stay below 1e-2 tol b_ref, and a recursive residual at most half
+            // the tolerance certifies the FP64 iterate, as the recursive residual of the FP64
+            // solve does
+            rr = pr.rr;
         } else if (small_update) {
             // r <- r - P A d with the FP32 operator: |A d| is about |r|, at most kSmallUpdate
             // tol b_ref, so its FP32 rounding (a few 1e-7 of |A d|) stays below 1e-2 tol b_ref
@@ -496,7 +505,7 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
         // the FP32 solve starts from its rounded copy, which every residual kernel of this
         // path writes beside r, with the FP64 r.r
         LCHK(c, launch_fill<float>(c->d32, 0.0f, n, s));
-        PcgResult pr;
+        pr = PcgResult{};
         // reduce the residual only as far as the outer tolerance still needs (half of the
         // remaining factor), but never ask FP32 for more than inner_tol
         const double need = 0.5 * c->opt.tol * bref / std::sqrt(rr);
@@ -1056,6 +1065,13 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         const double rr0 = c->opt.warm_start == NM_WS_COLD ? bref * bref : -1.0;
         if (c->opt.precision == NM_PREC_MIXED) {
             CHK(solve_mixed(c, c->w, bref, &local, rr0));
+            if (c->opt.true_residual) {
+                CHK(apply_A<double>(c, c->w, c->q, c->mask));
+                LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+                LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+                CHK(read_scalars(c));
+                local.relres = std::sqrt(c->hscal[S_RR]) / (bref > 0 ? bref : 1.0);
+            }
         } else {
             PcgResult r1;
             CHK(pcg<double>(c, c->b, c->w, c->r, c->p, c->q, true, false, bref, c->opt.tol, c->opt.max_iter,

@@ -3,7 +3,7 @@ any size (the oracle cannot run these grids in test time; its parity with the li
 established on the smaller grids of the other GPU tests):
 
 * 128^3 two-phase spheres and 256^3 Cu polycrystal: mixed precision stays within 1e-5
-  relative L2 of the FP64 solver, both converge to the 1e-8 true residual, and the Gamma
+  relative L2 of the FP64 solver, both reach the 1e-8 true (FP64) residual, and the Gamma
   voxels carry the prescribed displacement;
 * 512^3 Cu polycrystal with a spherical source (radius 6 at the centre) run with mixed
   precision and the learned start: convergence, Gamma values, and the device memory the
@@ -45,13 +45,15 @@ def test_mixed_within_1e5_of_fp64_at_full_size(case):
     steps = 6
     base = dict(tol=1e-8, max_iter=500, warm_start=nmb.WS_COLD)
     u64, st64 = _run(pb, nmb.Options(precision=nmb.PREC_FP64, true_residual=True, **base), steps)
-    u32, st32 = _run(pb, nmb.Options(precision=nmb.PREC_MIXED, inner_tol=1e-5, **base), steps)
+    # true_residual: the mixed solve's stopping test (FP64 residuals, then the recursive
+    # residual of a small final correction) must certify the FP64 residual of its iterate
+    u32, st32 = _run(pb, nmb.Options(precision=nmb.PREC_MIXED, inner_tol=1e-5, true_residual=True, **base), steps)
     errs = [np.linalg.norm(a - b) / np.linalg.norm(a) for a, b in zip(u64, u32) if np.abs(a).max() > 0]
     print(f"{case}: FP64 iters {[s['iters'][0] for s in st64]} true relres {max(s['relres'] for s in st64):.2e}; "
           f"mixed inner {[s['inner_iters'] for s in st32]} relres {max(s['relres'] for s in st32):.2e}; "
           f"max rel L2 mixed vs FP64 {max(errs):.2e}", flush=True)
     assert max(s["relres"] for s in st64) <= 1.01e-8
-    assert max(s["relres"] for s in st32) <= 1e-8
+    assert max(s["relres"] for s in st32) <= 1.01e-8
     assert max(errs) <= 1e-5
     _gamma_ok(pb, u64)
     _gamma_ok(pb, u32)

