@@ -469,7 +469,9 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
         } else if (small_update) {
             // r <- r - P A d with the FP32 operator: |A d| is about |r|, at most kSmallUpdate
             // tol b_ref, so its FP32 rounding (a few 1e-7 of |A d|) stays below 1e-2 tol b_ref
-            // and the stopping test still certifies the FP64 iterate
+            // and the stopping test still certifies the FP64 iterate.  d first takes the
+            // solve's last alpha p, which went only into x.
+            if (pr.iters > 0) LCHK(c, launch_axpy_scal<float>(c->d32, c->p32, c->scal + S_ALPHA, n, s));
             CHK(apply_A<float>(c, c->d32, c->q32, c->mask));
             LCHK(c, launch_update_f32q(c->r, c->q32, c->mask, c->N, c->part_a, s, c->r32));
             LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
@@ -509,12 +511,10 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
         // reduce the residual only as far as the outer tolerance still needs (half of the
         // remaining factor), but never ask FP32 for more than inner_tol
         const double need = 0.5 * c->opt.tol * bref / std::sqrt(rr);
-        // x += d; the correction itself is kept only where the next residual is an FP32 update
+        // x += d, the last PCG update folded in (d itself lacks it)
         CHK(pcg<float>(c, nullptr, c->d32, c->r32, c->p32, c->q32, true, true, std::sqrt(rr),
-                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr, rr,
-                       small_update ? nullptr : x));
+                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr, rr, x));
         inner += pr.iters;
-        if (small_update) LCHK(c, launch_add_f2d(x, c->d32, n, s));
         sweeps++;
     }
     if (st) {
