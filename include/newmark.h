@@ -93,7 +93,10 @@ typedef struct nm_step_stats {
     int iters[2];             /* FP64 solves: PCG iterations (Green route: u_b, u_f; projected: [0], [1] = 0) */
     int sweeps;               /* mixed precision: FP64 refinement sweeps */
     int inner_iters;          /* mixed precision: total FP32 PCG iterations */
-    double relres;            /* final relative residual (true residual when measured, else recursive) */
+    double relres;            /* final relative residual: the FP64 residual of the solution when
+                                 true_residual is set, else the value the stopping test used (the
+                                 recursive residual; in mixed precision the last FP64 residual or
+                                 a small final correction's recursive residual) */
     double relres0;           /* relative residual of the initial guess (first solve) */
     double t_step_ms;         /* wall time of the step (host clock, after a stream synchronize) */
     double t_warm_ms;         /* device time of the warm-start prediction (events on the stream) */
