@@ -543,8 +543,6 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     const int TX = TXC > 0 ? TXC : TXr;
     __shared__ V lds[BLK * R]; // TX * L <= BLK R
     __shared__ V twsm[L > 1 ? L : 2];
-    stage_twiddles<L>(twsm, tw);
-    __syncthreads();
     const int tid = threadIdx.x, c = tid % TX, t = tid / TX;
     const int M = sp.n1 / 2;
     const int kx = blockIdx.x * TX + c, ky = blockIdx.y;
@@ -553,29 +551,46 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     const uint32_t lane = (uint32_t)(c * sizeof(V)) + (uint32_t)t * (uint32_t)(colstride * sizeof(V));
     const uint32_t mstep = (uint32_t)(G * colstride * sizeof(V));
     auto at = [&](int j, int m) -> V& { return *(V*)((char*)(cb + j * NS) + (lane + (uint32_t)m * mstep)); };
+    // all three components' loads go out before the first transform (the barriers of
+    // the LDS exchanges would otherwise hold each load back behind the previous transform)
+    auto load3 = [&](V (&v)[3][R]) {
+#pragma unroll
+        for (int j = 0; j < 3; j++)
+#pragma unroll
+            for (int m = 0; m < R; m++) v[j][m] = at(j, m);
+    };
+    V u[3][R];
+    if constexpr (TXC > 0 && L >= 2 && sizeof(T) == 4) {
+        // full FP32 blocks: the twiddle loads go out first and the operands right behind
+        // them, so that only the twiddles are waited for before the barrier that publishes
+        // them (FP64, at one wave per SIMD, measured faster with the operands loaded after
+        // that barrier)
+        constexpr int NT = (L + BLK - 1) / BLK;
+        V twv[NT];
+#pragma unroll
+        for (int q = 0; q < NT; q++)
+            if (tid + q * BLK < L) twv[q] = tw[tw_offset(L) + tid + q * BLK];
+        load3(u);
+#pragma unroll
+        for (int q = 0; q < NT; q++)
+            if (tid + q * BLK < L) twsm[tid + q * BLK] = twv[q];
+        __syncthreads();
+    } else {
+        stage_twiddles<L>(twsm, tw);
+        __syncthreads();
+        load3(u);
+    }
     ColAddrT<TXC> addr{c, TX};
     const V* twL = twsm;
     const T xi1 = (T)(sp.k1 * kx);
-    const T xi2 = (T)(sp.k2 * freq_index(ky, sp.n2));
-
-    // all three components' loads go out before the first transform (the barriers of
-    // the LDS exchanges would otherwise hold each load back behind the previous transform)
-    V u[3][R];
-#pragma unroll
-    for (int j = 0; j < 3; j++)
-#pragma unroll
-        for (int m = 0; m < R; m++) u[j][m] = at(j, m);
-#pragma unroll
-    for (int j = 0; j < 3; j++) group_fft<L, R, -1>(u[j], t, lds, addr, twL);
+    const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
     // beta dt^2 K(xi) + rhobar I with K = N(xi)^T Cbar N(xi), N the Voigt strain of a plane
     // wave.  At fixed (xi1, xi2) it is quadratic in xi3: N = N12 + xi3 E3 (N12 holds the
     // xi1, xi2 entries, E3 the unit entries that xi3 multiplies), so
     //   beta dt^2 K + rhobar I = A0 + xi3 (A1 + xi3 A2)
     // with A0 = beta dt^2 N12^T C N12 + rhobar I, A1 = beta dt^2 (N12^T C E3 + E3^T C N12),
     // A2 = beta dt^2 E3^T C E3, formed once per thread (symmetric; upper triangles kept).
-    const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
-    T A0[6], A1[6], A2[6]; // order 00 01 02 11 12 22
-    {
+    auto form = [&](T x1, T x2, T (&A0)[6], T (&A1)[6], T (&A2)[6]) {
         T C[6][6];
         int o = 0;
 #pragma unroll
@@ -586,7 +601,6 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
                 C[b][a] = (T)sp.Cbar[o];
                 o++;
             }
-        const T x1 = xi1, x2 = xi2;
         T CN[6][3], CE[6][3];
 #pragma unroll
         for (int a = 0; a < 6; a++) {
@@ -612,7 +626,11 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
                 A2[q] = bdt2 * e3(CE, i, j);
                 q++;
             }
-    }
+    };
+#pragma unroll
+    for (int j = 0; j < 3; j++) group_fft<L, R, -1>(u[j], t, lds, addr, twL);
+    T A0[6], A1[6], A2[6]; // order 00 01 02 11 12 22
+    form(xi1, (T)(sp.k2 * freq_index(ky, sp.n2)), A0, A1, A2);
     // per-thread part of r . z in the working precision (24 products at most), summed in
     // FP64 across threads
     T part = 0;
@@ -652,6 +670,12 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
         u[1][m] = z1;
         u[2][m] = z2;
     }
+#pragma unroll
+    for (int j = 0; j < 3; j++) {
+        group_fft<L, R, +1>(u[j], t, lds, addr, twL);
+#pragma unroll
+        for (int m = 0; m < R; m++) at(j, m) = u[j][m];
+    }
     if (partials) {
         const double pd = (kx == 0 ? 1.0 : 2.0) * (double)part;
         double tot = 0.0;
@@ -671,12 +695,6 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
                 for (int i = 0; i < (int)blockDim.x; i++) tot += red1[i];
         }
         if (threadIdx.x == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
-    }
-#pragma unroll
-    for (int j = 0; j < 3; j++) {
-        group_fft<L, R, +1>(u[j], t, lds, addr, twL);
-#pragma unroll
-        for (int m = 0; m < R; m++) at(j, m) = u[j][m];
     }
 }
 
