@@ -41,8 +41,8 @@ OPERATOR_PASS_ID_BYTES = {"x_stress": 2, "x_inv_inertia": 2}
 # runs (profiles/hbm_traffic_256cube.md): FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the
 # factors a 512 MiB device copy reads for those counters.  Valid only for the kernel
 # sources they were taken on (hash below); otherwise the traffic is reported as null.
-PMC_TRAFFIC = {"kernel": "x_stress", "n": 256, "fetch_kib": 411477.2, "write_kib": 786432.0,
-               "fetch_scale": 2.000, "write_scale": 1.000, "sources_sha256_16": "43bc6ae2b2eccd5c"}
+PMC_TRAFFIC = {"kernel": "x_stress", "n": 256, "fetch_kib": 411485.2, "write_kib": 786432.0,
+               "fetch_scale": 2.000, "write_scale": 1.000, "sources_sha256_16": "e65e92da430114e3"}
 PMC_SOURCES = ("nm_common.h", "nm_fft.h", "nm_passes.h", "nm_passes.hip")
 
 
