@@ -15,14 +15,19 @@ from gpu_common import dev, field3, random_problem, rel_max
 
 pytestmark = pytest.mark.gpu
 
-CASES = [(3, (16, 8, 8)), (3, (64, 32, 16)), (3, (8, 16, 32)), (2, (64, 64)), (2, (16, 128)), (3, (32, 32, 32))]
+# the last two grids give the column passes full tiles of kx columns (the launch shape of
+# the large grids): (128, 16, 64) the z passes and the preconditioner z pass, (128, 64, 16)
+# the y passes; the others have fewer kx columns than one tile
+CASES = [(3, (16, 8, 8)), (3, (64, 32, 16)), (3, (8, 16, 32)), (2, (64, 64)), (2, (16, 128)), (3, (32, 32, 32)),
+         (3, (128, 16, 64)), (3, (128, 64, 16))]
+IDS = [f"{d}d-" + "x".join(map(str, n)) for d, n in CASES]
 
 
 def _ctx(pb):
     return nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10))
 
 
-@pytest.mark.parametrize("dim,n", CASES)
+@pytest.mark.parametrize("dim,n", CASES, ids=IDS)
 def test_apply_operator_matches_oracle(dim, n):
     import torch
     pb = random_problem(dim, n, seed=sum(n))
@@ -41,7 +46,7 @@ def test_apply_operator_matches_oracle(dim, n):
             assert err <= bar, err
 
 
-@pytest.mark.parametrize("dim,n", CASES)
+@pytest.mark.parametrize("dim,n", CASES, ids=IDS)
 def test_precond_matches_oracle(dim, n):
     import torch
     pb = random_problem(dim, n, seed=3 + sum(n))
