@@ -929,7 +929,9 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     CHK(dalloc(c, &c->Ubuf, 3 * std::max<long>(c->ng, 1)));
     CHK(dalloc(c, &c->gbuf, 3 * std::max<long>(c->ng, 1)));
     c->F_last.assign(c->dim * c->ng, 0.0);
-    // initial state (host dim x N -> device 3 x N)
+    // initial state (host dim x N -> device 3 x N); the zero fills queued on the stream
+    // above must land before these copies, whatever kind of stream the caller passed
+    HIPCHK(c, hipStreamSynchronize(s));
     if (pb->u0) HIPCHK(c, hipMemcpy(c->u, pb->u0, c->dim * c->N * sizeof(double), hipMemcpyHostToDevice));
     if (pb->v0) HIPCHK(c, hipMemcpy(c->v, pb->v0, c->dim * c->N * sizeof(double), hipMemcpyHostToDevice));
     if (pb->u0) {

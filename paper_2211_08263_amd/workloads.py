@@ -388,6 +388,49 @@ def make_polycrystal(n: int = 256, n_grains: int = 500, seed: int = 3, cfl: floa
                    pulse_fc=fc, n_steps=n_steps, tol=tol)
 
 
+def make_columnar_polycrystal(n: int = 256, n_grains: int = 500, seed: int = 3, cfl: float = 2.0,
+                              n_steps: int = 300, tol: float = 1e-8, axis: int = 2):
+    """Cu polycrystal whose grains are columns along one axis (a periodic 2D Voronoi
+    tessellation of the other two axes, extruded), on an n^3 grid.
+
+    Returns ``(full, reduced)``: the n^3 problem and the same problem on a grid with
+    one voxel along ``axis`` (dim 3; the transverse Voronoi map and the grain table are
+    shared).  Every field that does not vary along ``axis`` has the same image under the
+    discretized operator on both grids, so the reduced problem is a small stand-in for
+    the full one.  With axis == 2 the prescribed-displacement set is the x = 0 slab on
+    both grids; otherwise it is empty.  Time increment and pulse as in
+    make_polycrystal."""
+    rng = np.random.default_rng(seed)
+    red_n = [n, n, n]
+    red_n[axis] = 1
+    red_n = tuple(red_n)
+    phase_red = voronoi_periodic(red_n, n_grains, rng)  # shape (n3, n2, n1) with a 1 along axis
+    Rs = random_rotations(rng, n_grains)
+    C0 = copper_scaled66()
+    C = np.stack([voigt_to21(rotate_voigt66(C0, R)) for R in Rs])
+    rho = np.ones(n_grains)
+    dt = cfl / longitudinal_speed_max(C0, 1.0)
+    fc = math.sqrt(voigt_average66(C0)[0, 0]) / 8.0
+    np_axis = 2 - axis  # numpy axis of the grid axis
+    phase_full = np.ascontiguousarray(np.repeat(phase_red, n, axis=np_axis))
+    if axis == 2:
+        g_full, g_red = gamma_x_slab((n, n, n)), gamma_x_slab(red_n)
+    else:
+        g_full = g_red = np.zeros(0, np.int64)
+    full = Problem(f"columnar{n}", 3, (n, n, n), (float(n),) * 3, phase_full, C, rho, g_full, dt,
+                   pulse_fc=fc, n_steps=n_steps, tol=tol)
+    Lr = [float(n)] * 3
+    Lr[axis] = 1.0
+    red = Problem(f"columnar{n}-reduced", 3, red_n, tuple(Lr), phase_red, C, rho, g_red, dt,
+                  pulse_fc=fc, n_steps=n_steps, tol=tol)
+    return full, red
+
+
+def extrude_field(f: np.ndarray, n: int, axis: int) -> np.ndarray:
+    """Repeat a (dim, n3, n2, n1) field that has length 1 along grid axis ``axis`` n times."""
+    return np.ascontiguousarray(np.repeat(f, n, axis=3 - axis))
+
+
 def random_field(shape, seed: int, dtype=np.float64) -> np.ndarray:
     """i.i.d. N(0,1) field (operator micro-benchmark and parity input)."""
     return np.random.default_rng(seed).standard_normal(shape).astype(dtype)

@@ -44,3 +44,55 @@ def test_library_shares_the_hip_runtime_of_torch():
     nmb.load_library()
     rts = nmb.hip_runtimes_loaded()
     assert len(rts) == 1, rts
+
+
+def _bad_init(**change):
+    """nm_newmark_init on a small valid problem with one argument made invalid; every check
+    below fails before any device work, so these run without a GPU."""
+    import numpy as np
+    from paper_2211_08263_amd import newmark as nmb
+    from paper_2211_08263_amd import workloads as W
+    pb = W.make_polycrystal(n=16, n_grains=4, seed=1)
+    args = dict(dim=3, n=pb.n, L=pb.L, phase_id=pb.phase_id, C_voigt=pb.C21, rho=pb.rho, gamma_idx=pb.gamma_idx,
+                dt=pb.dt, options=nmb.Options())
+    args.update(change)
+    with pytest.raises(nmb.NewmarkError) as e:
+        nmb.newmark_init(**args)
+    return e.value.code
+
+
+@pytest.mark.parametrize("case,code", [
+    ("grid not a power of two", "EUNSUPPORTED"),
+    ("axis above 512", "EUNSUPPORTED"),
+    ("dim 4", "EUNSUPPORTED"),
+    ("2D with n3 > 1", "EUNSUPPORTED"),
+    ("duplicate Gamma index", "EINVAL"),
+    ("unsorted Gamma", "EINVAL"),
+    ("Gamma index out of range", "EINVAL"),
+    ("phase id out of range", "EINVAL"),
+    ("non-positive density", "EINVAL"),
+    ("non-positive dt", "EINVAL"),
+    ("non-positive tol", "EINVAL"),
+    ("unknown warm start", "EINVAL"),
+])
+def test_init_rejects_bad_arguments(case, code):
+    import numpy as np
+    from paper_2211_08263_amd import newmark as nmb
+    from paper_2211_08263_amd import workloads as W
+    pb = W.make_polycrystal(n=16, n_grains=4, seed=1)
+    g = pb.gamma_idx
+    change = {
+        "grid not a power of two": dict(n=(96, 16, 16), phase_id=np.zeros((16, 16, 96), np.uint16)),
+        "axis above 512": dict(n=(1024, 16, 16), phase_id=np.zeros((16, 16, 1024), np.uint16)),
+        "dim 4": dict(dim=4),
+        "2D with n3 > 1": dict(dim=2),
+        "duplicate Gamma index": dict(gamma_idx=np.concatenate([g[:3], g[2:3], g[3:]])),
+        "unsorted Gamma": dict(gamma_idx=g[::-1].copy()),
+        "Gamma index out of range": dict(gamma_idx=np.array([0, 16 ** 3], np.int64)),
+        "phase id out of range": dict(phase_id=np.full(pb.phase_id.shape, 7, np.uint16)),
+        "non-positive density": dict(rho=np.array([1.0, 0.0, 1.0, 1.0])),
+        "non-positive dt": dict(dt=0.0),
+        "non-positive tol": dict(options=nmb.Options(tol=0.0)),
+        "unknown warm start": dict(options=nmb.Options(warm_start=9)),
+    }[case]
+    assert _bad_init(**change) == getattr(nmb, "NM_" + code)

@@ -229,7 +229,7 @@ def test_learned_start_with_mixed_precision_keeps_the_solution():
         print(f"{gamma}: learned+mixed vs FP64 max rel L2 {max(errs):.2e}, relres "
               f"{max(x['relres'] for x in res['mixed_learned'][1]):.2e}, sweeps "
               f"{[x['sweeps'] for x in res['mixed_learned'][1]]}", flush=True)
-        assert max(x["relres"] for x in res["mixed_learned"][1]) <= 1.01e-9  # FP64 residual of the iterate
+        assert max(x["relres"] for x in res["mixed_learned"][1]) <= 1e-9  # FP64 residual of the iterate
         assert max(errs) < 1e-5
         for s, u in enumerate(res["mixed_learned"][0]):
             want = pb.U(s + 1)
@@ -418,3 +418,32 @@ def test_solver_inference_matches_the_full_network():
             w = net.get_params()
             net.set_params(w * 1.05)
     net.close()
+
+
+def test_trained_start_on_a_held_out_trajectory():
+    """The shipped weights on a polycrystal none of the training trajectories used (64^3,
+    8 grains, seed 1099): per-step initial relative residual, PCG iterations and step time
+    for the cold (zero), previous-step and learned initial iterates, FP64 solver to 1e-8.
+    The learned iterate must start closer to the solution than both (lower geometric-mean
+    initial residual) and need no more iterations than the cold start; the iteration
+    counts and times are recorded (see the printout)."""
+    from paper_2211_08263_amd import warmstart
+    pb = W.make_polycrystal(n=64, n_grains=8, seed=1099, n_steps=30)
+    net = nmb.Net()
+    assert warmstart.load_weights(net)
+    res = {}
+    for name, ws in (("cold", nmb.WS_COLD), ("prev", nmb.WS_PREV), ("learned", nmb.WS_LEARNED)):
+        with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-8, max_iter=500, warm_start=ws)) as ctx:
+            if ws == nmb.WS_LEARNED:
+                nmb.ws_attach(ctx, net)
+            st = [nmb.newmark_step(ctx, pb.U(s + 1)) for s in range(24)]
+        st = st[4:]  # from rest the first steps carry almost no signal
+        res[name] = {"iters": float(np.mean([x["iters"][0] for x in st])),
+                     "relres0": float(np.exp(np.mean([np.log(max(x["relres0"], 1e-300)) for x in st]))),
+                     "ms": float(np.median([x["t_step_ms"] for x in st]))}
+    net.close()
+    print("held-out 64^3 trajectory:", {k: {kk: round(vv, 3) for kk, vv in v.items()} for k, v in res.items()},
+          flush=True)
+    assert res["learned"]["relres0"] < 0.8 * res["cold"]["relres0"]
+    assert res["learned"]["relres0"] < 0.8 * res["prev"]["relres0"]
+    assert res["learned"]["iters"] <= res["cold"]["iters"]

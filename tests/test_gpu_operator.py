@@ -1,8 +1,12 @@
 """GPU parity of the operator A and the preconditioner M against the FP64 oracle.
 
 Sizes span several blocks and a partial last block of x lines; the inputs are
-i.i.d. normal fields (every frequency bin including the Nyquist ones).
-Bars: FP64 max relative error <= 1e-12, FP32 <= 2e-5 (relative to the
+i.i.d. normal fields (every frequency bin including the Nyquist ones).  The
+last six grids hold 2^20 voxels, so the spectra use the padded component
+stride of the large grids, and each puts a 256- or 512-long axis in x, y and z
+in turn: every axis length the benchmark grids compile to is compared with the
+oracle element by element.
+Bars: FP64 max relative error <= 1e-12, FP32 <= 1e-5 (relative to the
 largest output entry)."""
 import numpy as np
 import pytest
@@ -19,7 +23,9 @@ pytestmark = pytest.mark.gpu
 # the large grids): (128, 16, 64) the z passes and the preconditioner z pass, (128, 64, 16)
 # the y passes; the others have fewer kx columns than one tile
 CASES = [(3, (16, 8, 8)), (3, (64, 32, 16)), (3, (8, 16, 32)), (2, (64, 64)), (2, (16, 128)), (3, (32, 32, 32)),
-         (3, (128, 16, 64)), (3, (128, 64, 16))]
+         (3, (128, 16, 64)), (3, (128, 64, 16)),
+         (3, (256, 64, 64)), (3, (64, 256, 64)), (3, (64, 64, 256)),
+         (3, (512, 64, 32)), (3, (32, 512, 64)), (3, (32, 64, 512))]
 IDS = [f"{d}d-" + "x".join(map(str, n)) for d, n in CASES]
 
 
@@ -35,7 +41,7 @@ def test_apply_operator_matches_oracle(dim, n):
     u = W.random_field(op.field_shape, seed=7)
     want = field3(op.apply(u), dim)
     with _ctx(pb) as ctx:
-        for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+        for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
             ud = dev(field3(u, dim), dtype)
             out = torch.empty_like(ud)
             nmb.apply_operator(ctx, ud, out)
@@ -54,7 +60,7 @@ def test_precond_matches_oracle(dim, n):
     r = W.random_field(op.field_shape, seed=8)
     want = field3(op.precond(r), dim)
     with _ctx(pb) as ctx:
-        for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 2e-5)):
+        for dtype, bar in ((torch.float64, 1e-12), (torch.float32, 1e-5)):
             rd = dev(field3(r, dim), dtype)
             out = torch.empty_like(rd)
             nmb.precond_apply(ctx, rd, out)
