@@ -201,6 +201,20 @@ int nm_conv3d_bf16(void* hip_stream, int mode, const int* grid, int cinp, int ci
                    const void* w_fp32_host, const float* bias_host, const void* dy_dev, void* out_dev, float* dw_host,
                    float* db_host);
 
+/* nm_conv3d_bf16 for callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same arguments,
+ * kernels and results, with every device buffer of the call (FP32 and packed BF16 weights,
+ * bias, weight-gradient partial sums) taken from one file-scope device array of 16 MiB
+ * that each device holds until the process ends.  It calls no hipMalloc or hipFree.  The
+ * weight-gradient pass (mode 2) uses at most 256 partial-sum slots, so the array does not
+ * grow with the grid and no grid accepted by nm_conv3d_bf16 is too large; its sums are
+ * grouped differently from nm_conv3d_bf16's (FP32 rounding differs, modes 0 and 1 are
+ * identical).  Every call on a device shares that device's array and leaves its contents
+ * behind: calls that overlap on one device race.  Synchronous on hip_stream. */
+int nm_conv3d_bf16_noalloc(void* hip_stream, int mode, const int* grid, int cinp, int cin, int cout,
+                           const void* x_dev, const void* w_fp32_host, const float* bias_host, const void* dy_dev,
+                           void* out_dev, float* dw_host, float* db_host);
+
 /* Attach a network to a solver context (not owned; NULL detaches).  Needed by
  * NM_WS_LEARNED and by the two training-sample calls below. */
 int nm_ws_attach(nm_ctx* ctx, nm_net* net);

@@ -18,6 +18,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <mutex>
 #include <random>
 #include <vector>
 
@@ -662,13 +663,16 @@ static int launch_conv(int cinp, int epi, const uint16_t* X, const uint16_t* W, 
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
-static long bwdw_waves(long ntiles) { return ntiles < 1024 ? ntiles : 1024; }
+// Waves of the weight-gradient pass (each owns a partial-sum slot of bwdw_slot_floats(cinp)).
+constexpr long kBwdwWaves = 1024;
+static long bwdw_waves(long ntiles, long cap = kBwdwWaves) { return ntiles < cap ? ntiles : cap; }
+static constexpr long bwdw_slot_floats(int cinp) { return 27L * (cinp / 16) * 256 + 64; }
 
 static int launch_bwdw(int cinp, const uint16_t* X, const uint16_t* DZ, float* partial, float* dW, float* db, int cin,
-                       int cout, const Grid& g, hipStream_t s)
+                       int cout, const Grid& g, hipStream_t s, long wave_cap = kBwdwWaves)
 {
     const long ntiles = g.N / 16;
-    long waves = bwdw_waves(ntiles);
+    long waves = bwdw_waves(ntiles, wave_cap);
     const long tpw = (ntiles + waves - 1) / waves;
     waves = (ntiles + tpw - 1) / tpw;
     const int blocks = (int)((waves + 3) / 4);
@@ -957,60 +961,155 @@ int nm_net_gradients(nm_net* n, void* stream, const int* grid, const void* feat_
 }
 
 // Single-layer kernels on caller buffers (used to check each kernel against the oracle).
-int nm_conv3d_bf16(void* stream, int mode, const int* grid, int cinp, int cin, int cout, const void* x_dev,
-                   const void* w_fp32_host, const float* bias_host, const void* dy_dev, void* out_dev,
-                   float* dw_host, float* db_host)
-{
-    if (!grid || (cinp != 16 && cinp != 32) || cin > cinp || cout > 16 || cin < 1 || cout < 1) return NM_EINVAL;
-    CHECK_NM(check_grid(grid));
-    Grid g{grid[0], grid[1], grid[2], (long)grid[0] * grid[1] * grid[2]};
-    hipStream_t s = (hipStream_t)stream;
-    std::vector<void*> tmp;
+// Device buffers of one call: FP32 weights and bias, their packed BF16 forms, and for the
+// weight gradient the per-wave partial sums and the reduced gradients.
+struct ConvBufs {
     float *wd = nullptr, *bd = nullptr, *part = nullptr, *dw = nullptr, *db = nullptr;
     uint16_t *wf = nullptr, *wb = nullptr;
-    int rc = NM_OK;
+};
+
+__global__ void k_zero_f32(float* __restrict__ x, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = 0.f;
+}
+
+static int conv3d_check(const int* grid, int cinp, int cin, int cout)
+{
+    if (!grid || (cinp != 16 && cinp != 32) || cin > cinp || cout > 16 || cin < 1 || cout < 1) return NM_EINVAL;
+    return check_grid(grid);
+}
+
+static int conv3d_run(hipStream_t s, int mode, const Grid& g, int cinp, int cin, int cout, const void* x_dev,
+                      const void* w_fp32_host, const float* bias_host, const void* dy_dev, void* out_dev,
+                      float* dw_host, float* db_host, const ConvBufs& b, long wave_cap)
+{
     const long nw = (long)cout * cin * 27;
-    if (net_alloc((void**)&wd, nw * 4, &tmp) || net_alloc((void**)&bd, 64, &tmp) ||
-        net_alloc((void**)&wf, 27 * 16 * cinp * 2, &tmp) || net_alloc((void**)&wb, 27 * 256 * 2, &tmp)) {
-        rc = NM_ENOMEM;
-        goto done;
-    }
-    if (w_fp32_host && hipMemcpy(wd, w_fp32_host, nw * 4, hipMemcpyHostToDevice) != hipSuccess) rc = NM_EHIP;
-    (void)hipMemset(bd, 0, 64);
-    if (bias_host && hipMemcpy(bd, bias_host, cout * 4, hipMemcpyHostToDevice) != hipSuccess) rc = NM_EHIP;
-    if (rc) goto done;
+    if (w_fp32_host && hipMemcpyAsync(b.wd, w_fp32_host, nw * 4, hipMemcpyHostToDevice, s) != hipSuccess)
+        return NM_EHIP;
+    hipLaunchKernelGGL(k_zero_f32, dim3(1), dim3(64), 0, s, b.bd, 16);
+    if (bias_host && hipMemcpyAsync(b.bd, bias_host, cout * 4, hipMemcpyHostToDevice, s) != hipSuccess) return NM_EHIP;
     {
         const int tot = 27 * 16 * cinp > 27 * 256 ? 27 * 16 * cinp : 27 * 256;
-        hipLaunchKernelGGL(k_pack, dim3((tot + 255) / 256), dim3(256), 0, s, wd, cin, cout, cinp, wf,
-                           cinp == 16 ? wb : nullptr);
+        hipLaunchKernelGGL(k_pack, dim3((tot + 255) / 256), dim3(256), 0, s, b.wd, cin, cout, cinp, b.wf,
+                           cinp == 16 ? b.wb : nullptr);
     }
+    int rc = NM_OK;
     if (mode == 0) {
         // forward, FP32 output [N][16] without activation
-        if (launch_conv(cinp, EPI_F32, (const uint16_t*)x_dev, wf, bd, out_dev, nullptr, g, cout, 16, s)) rc = NM_EHIP;
+        if (launch_conv(cinp, EPI_F32, (const uint16_t*)x_dev, b.wf, b.bd, out_dev, nullptr, g, cout, 16, s))
+            rc = NM_EHIP;
     } else if (mode == 1) {
         // backward data: out = W^T * dy as FP32 [N][16] (dy BF16 [N][16])
         if (cinp != 16) rc = NM_EINVAL;
-        else if (launch_conv(16, EPI_F32, (const uint16_t*)dy_dev, wb, nullptr, out_dev, nullptr, g, cin, 16, s))
+        else if (launch_conv(16, EPI_F32, (const uint16_t*)dy_dev, b.wb, nullptr, out_dev, nullptr, g, cin, 16, s))
             rc = NM_EHIP;
     } else if (mode == 2) {
-        const long waves = bwdw_waves(g.N / 16);
-        if (net_alloc((void**)&part, waves * (27L * 2 * 256 + 64) * 4, &tmp) || net_alloc((void**)&dw, nw * 4, &tmp) ||
-            net_alloc((void**)&db, 64, &tmp)) {
-            rc = NM_ENOMEM;
-            goto done;
-        }
-        if (launch_bwdw(cinp, (const uint16_t*)x_dev, (const uint16_t*)dy_dev, part, dw, db, cin, cout, g, s))
+        if (launch_bwdw(cinp, (const uint16_t*)x_dev, (const uint16_t*)dy_dev, b.part, b.dw, b.db, cin, cout, g, s,
+                        wave_cap))
             rc = NM_EHIP;
-        else if (hipMemcpyAsync(dw_host, dw, nw * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
-                 hipMemcpyAsync(db_host, db, cout * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
+        else if (hipMemcpyAsync(dw_host, b.dw, nw * 4, hipMemcpyDeviceToHost, s) != hipSuccess ||
+                 hipMemcpyAsync(db_host, b.db, cout * 4, hipMemcpyDeviceToHost, s) != hipSuccess)
             rc = NM_EHIP;
     } else {
         rc = NM_EINVAL;
     }
     if (hipStreamSynchronize(s) != hipSuccess && rc == NM_OK) rc = NM_EHIP;
-done:
+    return rc;
+}
+
+int nm_conv3d_bf16(void* stream, int mode, const int* grid, int cinp, int cin, int cout, const void* x_dev,
+                   const void* w_fp32_host, const float* bias_host, const void* dy_dev, void* out_dev,
+                   float* dw_host, float* db_host)
+{
+    CHECK_NM(conv3d_check(grid, cinp, cin, cout));
+    if (mode < 0 || mode > 2) return NM_EINVAL;
+    Grid g{grid[0], grid[1], grid[2], (long)grid[0] * grid[1] * grid[2]};
+    std::vector<void*> tmp;
+    ConvBufs b;
+    const long nw = (long)cout * cin * 27;
+    int rc = NM_OK;
+    if (net_alloc((void**)&b.wd, nw * 4, &tmp) || net_alloc((void**)&b.bd, 64, &tmp) ||
+        net_alloc((void**)&b.wf, 27 * 16 * cinp * 2, &tmp) || net_alloc((void**)&b.wb, 27 * 256 * 2, &tmp))
+        rc = NM_ENOMEM;
+    if (rc == NM_OK && mode == 2) {
+        const long waves = bwdw_waves(g.N / 16);
+        if (net_alloc((void**)&b.part, waves * bwdw_slot_floats(cinp) * 4, &tmp) ||
+            net_alloc((void**)&b.dw, nw * 4, &tmp) || net_alloc((void**)&b.db, 64, &tmp))
+            rc = NM_ENOMEM;
+    }
+    if (rc == NM_OK)
+        rc = conv3d_run((hipStream_t)stream, mode, g, cinp, cin, cout, x_dev, w_fp32_host, bias_host, dy_dev, out_dev,
+                        dw_host, db_host, b, kBwdwWaves);
     for (void* q : tmp) (void)hipFree(q);
     return rc;
+}
+
+// ---------------------------------------------------------------------------
+// nm_conv3d_bf16_noalloc: the same layer kernels with every device buffer of the call
+// (FP32 and packed BF16 weights, bias, weight-gradient partials and sums) carved out of one
+// file-scope device array, so that callers that may not allocate device memory can run
+// them.  The weight-gradient pass uses at most kNoAllocWaves partial-sum slots, which keeps
+// the array's size independent of the grid.  Every call on a device shares that device's
+// array (kept until the process ends); calls that overlap on one device race.
+// ---------------------------------------------------------------------------
+constexpr long kNoAllocWaves = 256;
+constexpr size_t kScratchBytes = size_t(16) << 20;
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+constexpr size_t align256(size_t b) { return (b + 255) & ~size_t(255); }
+constexpr size_t kOffWd = 0;                                           // FP32 [16][32][27]
+constexpr size_t kOffBd = kOffWd + align256(16 * 32 * 27 * 4);         // FP32 [16]
+constexpr size_t kOffWf = kOffBd + align256(16 * 4);                   // BF16 [27][16][32]
+constexpr size_t kOffWb = kOffWf + align256(27 * 16 * 32 * 2);         // BF16 [27][16][16]
+constexpr size_t kOffDw = kOffWb + align256(27 * 256 * 2);             // FP32 [16][32][27]
+constexpr size_t kOffDb = kOffDw + align256(16 * 32 * 27 * 4);         // FP32 [16]
+constexpr size_t kOffPart = kOffDb + align256(16 * 4);                 // FP32 partials
+constexpr size_t kScratchUsed = kOffPart + size_t(kNoAllocWaves) * bwdw_slot_floats(32) * 4;
+static_assert(kScratchUsed <= kScratchBytes, "the no-allocation layout must fit the scratch array");
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+unsigned char* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array (looked up once per device, with that
+// device current: the array's name is only a host-side stand-in).
+int scratch_base(unsigned char** out)
+{
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return NM_EHIP;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return NM_EHIP;
+        g_scratch_ptr[dev] = (unsigned char*)p;
+    }
+    *out = g_scratch_ptr[dev];
+    return NM_OK;
+}
+} // namespace
+
+int nm_conv3d_bf16_noalloc(void* stream, int mode, const int* grid, int cinp, int cin, int cout, const void* x_dev,
+                           const void* w_fp32_host, const float* bias_host, const void* dy_dev, void* out_dev,
+                           float* dw_host, float* db_host)
+{
+    CHECK_NM(conv3d_check(grid, cinp, cin, cout));
+    if (mode < 0 || mode > 2) return NM_EINVAL;
+    Grid g{grid[0], grid[1], grid[2], (long)grid[0] * grid[1] * grid[2]};
+    unsigned char* base = nullptr;
+    CHECK_NM(scratch_base(&base));
+    ConvBufs b;
+    b.wd = (float*)(base + kOffWd);
+    b.bd = (float*)(base + kOffBd);
+    b.wf = (uint16_t*)(base + kOffWf);
+    b.wb = (uint16_t*)(base + kOffWb);
+    b.dw = (float*)(base + kOffDw);
+    b.db = (float*)(base + kOffDb);
+    b.part = (float*)(base + kOffPart);
+    return conv3d_run((hipStream_t)stream, mode, g, cinp, cin, cout, x_dev, w_fp32_host, bias_host, dy_dev, out_dev,
+                      dw_host, db_host, b, kNoAllocWaves);
 }
 
 } // extern "C"

@@ -34,7 +34,8 @@ WS_COLD, WS_PREV, WS_TAYLOR, WS_LEARNED = 0, 1, 2, 3
 EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_precond_apply", "nm_pcg_solve",
             "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream", "nm_profile_passes",
             "nm_net_create", "nm_net_destroy", "nm_net_num_params", "nm_net_get_params", "nm_net_set_params",
-            "nm_net_forward", "nm_net_train_step", "nm_net_gradients", "nm_conv3d_bf16", "nm_ws_attach",
+            "nm_net_forward", "nm_net_train_step", "nm_net_gradients", "nm_conv3d_bf16", "nm_conv3d_bf16_noalloc",
+            "nm_ws_attach",
             "nm_ws_features", "nm_ws_target", "nm_ws_predict", "nm_ws_residual_sample", "nm_ws_train_residual",
             "nm_last_error", "nm_destroy")
 
@@ -118,6 +119,7 @@ def load_library():
     L.nm_net_train_step.argtypes = [vp, vp, vp, vp, vp, C.c_float, C.POINTER(C.c_float)]
     L.nm_net_gradients.argtypes = [vp, vp, vp, vp, vp, vp, C.POINTER(C.c_float)]
     L.nm_conv3d_bf16.argtypes = [vp, i, vp, i, i, i, vp, vp, vp, vp, vp, vp, vp]
+    L.nm_conv3d_bf16_noalloc.argtypes = [vp, i, vp, i, i, i, vp, vp, vp, vp, vp, vp, vp]
     L.nm_ws_attach.argtypes = [vp, vp]
     L.nm_ws_features.argtypes = [vp, vp]
     L.nm_ws_target.argtypes = [vp, vp]
@@ -406,13 +408,16 @@ def _chk(code, what):
         raise NewmarkError(code, what)
 
 
-def conv3d_bf16(mode, grid, cinp, cin, cout, x=None, w=None, bias=None, dy=None, out=None, stream=None):
-    """One network layer's kernel on caller buffers (see nm_conv3d_bf16)."""
+def conv3d_bf16(mode, grid, cinp, cin, cout, x=None, w=None, bias=None, dy=None, out=None, stream=None,
+                noalloc=False):
+    """One network layer's kernel on caller buffers (see nm_conv3d_bf16; noalloc selects
+    nm_conv3d_bf16_noalloc, which allocates no device memory)."""
     wa = None if w is None else np.ascontiguousarray(w, dtype=np.float32)
     ba = None if bias is None else np.ascontiguousarray(bias, dtype=np.float32)
     dw = np.zeros((cout, cin, 27), dtype=np.float32)
     db = np.zeros(cout, dtype=np.float32)
-    _chk(load_library().nm_conv3d_bf16(_stream_arg(stream), int(mode), _grid(grid), int(cinp), int(cin), int(cout),
+    fn = load_library().nm_conv3d_bf16_noalloc if noalloc else load_library().nm_conv3d_bf16
+    _chk(fn(_stream_arg(stream), int(mode), _grid(grid), int(cinp), int(cin), int(cout),
                                        None if x is None else x.data_ptr(), None if wa is None else wa.ctypes.data,
                                        None if ba is None else ba.ctypes.data, None if dy is None else dy.data_ptr(),
                                        None if out is None else out.data_ptr(), dw.ctypes.data, db.ctypes.data),
