@@ -781,6 +781,124 @@ out:
 }
 
 /* ------------------------------------------------------------------------- */
+/* Explicit central-difference scheme (section 2.3)                           */
+/* ------------------------------------------------------------------------- */
+
+/*
+ * Newmark with beta = 0, gamma = 1/2 (eq. Central_diff_rule): per step
+ *     u_n   = u_{n-1} + dt v_{n-1} + dt^2/2 a_{n-1}
+ *     vb    = v_{n-1} + dt/2 a_{n-1} + dt/(2 rho) div(C : grad^s u_n)   (eq. b_explicit, 3D form)
+ *     f_n   = 2 rho / dt (Udot_n - vb) on Gamma, 0 elsewhere
+ *     v_n   = vb + dt/(2 rho) f_n                      (eq. Explicit_linear_momentum_arranged_3D)
+ *     a_n   = (div(C : grad^s u_n) + f_n) / rho        (so that v_n = v_{n-1} + dt/2 (a_{n-1} + a_n))
+ * The velocity is prescribed on Gamma (Udot: d values per step, uniform on Gamma, when
+ * per_point == 0, else d * n_gamma values per step, point major).  The initial
+ * acceleration is a0 = div(C : grad^s u0) / rho.  p->beta and p->gamma_nm are not used.
+ * u_hist (n_steps x d x N), v_hist and F_hist (n_steps x d * n_gamma, the nodal force f_n
+ * on Gamma) may be NULL; v_out and a_out receive the final velocity and acceleration.
+ */
+int or_explicit(const or_prob *p, const int64_t *gidx, int n_gamma, int n_steps, const double *Udot,
+                int per_point, const double *u0, const double *v0, double *u_hist, double *v_hist,
+                double *F_hist, double *v_out, double *a_out)
+{
+    int d = p->d;
+    long N = nvox(p), n = (long)d * N;
+    int nd = d * n_gamma;
+    double dt = p->dt;
+    double *u = calloc(n, sizeof(double)), *v = calloc(n, sizeof(double)),
+           *a = calloc(n, sizeof(double)), *sd = malloc(sizeof(double) * n),
+           *f = malloc(sizeof(double) * n);
+    if (u0)
+        memcpy(u, u0, sizeof(double) * n);
+    if (v0)
+        memcpy(v, v0, sizeof(double) * n);
+    or_div_stress(p, u, a);
+    for (int j = 0; j < d; j++)
+        for (long x = 0; x < N; x++)
+            a[j * N + x] /= p->rho[p->phase[x]];
+    for (int s = 0; s < n_steps; s++) {
+        const double *Us = Udot + (long)s * (per_point ? nd : d);
+        for (long i = 0; i < n; i++)
+            u[i] = u[i] + dt * v[i] + 0.5 * dt * dt * a[i];
+        or_div_stress(p, u, sd);
+        /* vb into v; f zero off Gamma */
+        for (int j = 0; j < d; j++)
+            for (long x = 0; x < N; x++) {
+                long i = j * N + x;
+                double r = p->rho[p->phase[x]];
+                v[i] = v[i] + 0.5 * dt * a[i] + dt / (2.0 * r) * sd[i];
+                f[i] = 0.0;
+            }
+        for (int pt = 0; pt < n_gamma; pt++)
+            for (int j = 0; j < d; j++) {
+                long i = j * N + gidx[pt];
+                double r = p->rho[p->phase[gidx[pt]]];
+                double Ud = per_point ? Us[d * pt + j] : Us[j];
+                f[i] = 2.0 * r / dt * (Ud - v[i]);
+                if (F_hist)
+                    F_hist[(long)s * nd + d * pt + j] = f[i];
+            }
+        for (int j = 0; j < d; j++)
+            for (long x = 0; x < N; x++) {
+                long i = j * N + x;
+                double r = p->rho[p->phase[x]];
+                v[i] = v[i] + dt / (2.0 * r) * f[i];
+                a[i] = (sd[i] + f[i]) / r;
+            }
+        if (u_hist)
+            memcpy(u_hist + (long)s * n, u, sizeof(double) * n);
+        if (v_hist)
+            memcpy(v_hist + (long)s * n, v, sizeof(double) * n);
+    }
+    if (v_out)
+        memcpy(v_out, v, sizeof(double) * n);
+    if (a_out)
+        memcpy(a_out, a, sizeof(double) * n);
+    free(u); free(v); free(a); free(sd); free(f);
+    return 0;
+}
+
+/*
+ * Largest eigenvalue omega_max^2 of the discrete problem K x = omega^2 rho x, K = -div(C :
+ * grad^s .) (section 2.3.3: the stable increment of eq. Courant_stable is 2 / omega_max), by
+ * power iteration on rho^-1 K from the start vector x (d x N, overwritten by the last
+ * iterate, normalised in the rho-weighted norm).  Returns the Rayleigh quotient
+ * x.K x / x.rho x of the last iterate after `iters` products.
+ */
+double or_omega2_max(const or_prob *p, double *x, int iters)
+{
+    int d = p->d;
+    long N = nvox(p), n = (long)d * N;
+    double *y = malloc(sizeof(double) * n);
+    double lam = 0.0;
+    for (int it = 0; it <= iters; it++) {
+        /* normalise: x.rho x = 1 */
+        double m = 0.0;
+        for (int j = 0; j < d; j++)
+            for (long v = 0; v < N; v++)
+                m += p->rho[p->phase[v]] * x[j * N + v] * x[j * N + v];
+        double sc = 1.0 / sqrt(m);
+        for (long i = 0; i < n; i++)
+            x[i] *= sc;
+        /* y = K x ; lam = x.K x */
+        or_div_stress(p, x, y);
+        lam = 0.0;
+        for (long i = 0; i < n; i++) {
+            y[i] = -y[i];
+            lam += x[i] * y[i];
+        }
+        if (it == iters)
+            break;
+        /* x <- rho^-1 K x */
+        for (int j = 0; j < d; j++)
+            for (long v = 0; v < N; v++)
+                x[j * N + v] = y[j * N + v] / p->rho[p->phase[v]];
+    }
+    free(y);
+    return lam;
+}
+
+/* ------------------------------------------------------------------------- */
 /* Direct 3x3x3 periodic convolution (learned warm start)                     */
 /* ------------------------------------------------------------------------- */
 

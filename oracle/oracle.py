@@ -56,6 +56,10 @@ def lib():
         L.or_green_matrix.restype = i
         L.or_newmark.argtypes = [P, vp, i, C.POINTER(_Opts), i, vp, i, vp, vp, vp, vp, vp, vp, vp]
         L.or_newmark.restype = i
+        L.or_explicit.argtypes = [P, vp, i, i, vp, i, vp, vp, vp, vp, vp, vp, vp]
+        L.or_explicit.restype = i
+        L.or_omega2_max.argtypes = [P, vp, i]
+        L.or_omega2_max.restype = d
         L.or_conv3d_fwd.argtypes = [vp, vp, vp, vp, i, i, vp]
         L.or_conv3d_bwd_data.argtypes = [vp, vp, vp, i, i, vp]
         L.or_conv3d_bwd_weight.argtypes = [vp, vp, vp, vp, i, i, vp]
@@ -207,6 +211,32 @@ class OracleProblem:
         if st != 0:
             raise RuntimeError("oracle Newmark failed with status %d" % st)
         return {"u": uh, "iters": its, "F": Fh, "v": v, "a": a}
+
+
+    def explicit(self, gamma_idx, Udot, n_steps, per_point=False, u0=None, v0=None, want_v=False, want_F=False):
+        """Central-difference run (beta = 0, gamma = 1/2) with the velocity Udot prescribed on
+        Gamma; returns dict(u=(n_steps, d, ...), v (history if want_v), F, v_last, a_last)."""
+        g = np.ascontiguousarray(gamma_idx, dtype=np.int64)
+        Ud = _f64(Udot).reshape(-1)
+        uh = np.empty((n_steps,) + self.field_shape)
+        vh = np.empty((n_steps,) + self.field_shape) if want_v else None
+        Fh = np.empty((n_steps, self.dim * g.size)) if want_F else None
+        v = np.empty(self.field_shape)
+        a = np.empty(self.field_shape)
+        u0a = None if u0 is None else self._vec(u0)
+        v0a = None if v0 is None else self._vec(v0)
+        st = lib().or_explicit(C.byref(self.s), _p(g), int(g.size), int(n_steps), _p(Ud), int(bool(per_point)),
+                               _p(u0a), _p(v0a), _p(uh), _p(vh), _p(Fh), _p(v), _p(a))
+        if st != 0:
+            raise RuntimeError("oracle explicit run failed")
+        return {"u": uh, "v": vh, "F": Fh, "v_last": v, "a_last": a}
+
+    def omega2_max(self, x0, iters):
+        """Power-iteration estimate of the largest omega^2 of K x = omega^2 rho x from the start
+        vector x0; returns (omega^2, last normalised iterate)."""
+        x = self._vec(x0).copy()
+        lam = lib().or_omega2_max(C.byref(self.s), _p(x), int(iters))
+        return float(lam), x
 
 
 # --- free functions ------------------------------------------------------------

@@ -281,6 +281,16 @@ def ricker(t, fc: float, t0: Optional[float] = None, amp: float = 1.0):
     return amp * (1 - 2 * a) * np.exp(-a)
 
 
+def ricker_rate(t, fc: float, t0: Optional[float] = None, amp: float = 1.0):
+    """Time derivative of ricker(): the prescribed velocity of the explicit scheme's source.
+    With a = (pi fc tau)^2: d/dt [(1 - 2a) e^-a] = 2 pi^2 fc^2 tau (2a - 3) e^-a."""
+    if t0 is None:
+        t0 = 2.0 / fc
+    tau = np.asarray(t, dtype=np.float64) - t0
+    a = (np.pi * fc * tau) ** 2
+    return amp * 2.0 * (np.pi * fc) ** 2 * tau * (2 * a - 3) * np.exp(-a)
+
+
 def bell_pulse(t, A: float, omega: float, alpha: float = 4.0):
     """Bell pulse of the paper's 1D tests (section 3.1): A (t (T - t))^alpha / (T^2/4)^alpha on [0, T], T = pi/omega."""
     T = math.pi / omega
@@ -318,6 +328,13 @@ class Problem:
     def U(self, step: int) -> np.ndarray:
         """Prescribed displacement vector (dim values, uniform on Gamma) at t_step = step * dt."""
         a = float(ricker(step * self.dt, self.pulse_fc)) if self.pulse_fc > 0 else 0.0
+        return np.array(self.pulse_dir[: self.dim], dtype=np.float64) * a
+
+    def Udot(self, step: int, dt: Optional[float] = None) -> np.ndarray:
+        """Prescribed velocity (the rate of U) at t_step = step * dt (dt defaults to the
+        problem's; the explicit scheme runs at its own stable increment)."""
+        h = self.dt if dt is None else dt
+        a = float(ricker_rate(step * h, self.pulse_fc)) if self.pulse_fc > 0 else 0.0
         return np.array(self.pulse_dir[: self.dim], dtype=np.float64) * a
 
 
