@@ -104,7 +104,8 @@ typedef struct nm_step_stats {
 
 typedef struct nm_ctx nm_ctx;
 
-/* Build the solver: copies the problem to the device, forms the reference
+/* Build the solver (beta > 0: the implicit Newmark method; beta == 0: the explicit
+ * central-difference scheme, see nm_explicit_step): copies the problem to the device, forms the reference
  * medium (volume averages of C and rho, eq. (precond)), the FFT twiddle
  * tables, the Gamma route (GREEN: d*n_gamma unit-force solves of eq.
  * (solve_green), the matrix G of eq. (G) and its LU factors) and the initial
@@ -117,6 +118,32 @@ int nm_newmark_init(const nm_problem* pb, const nm_options* op, void* hip_stream
  * dim*n_gamma values (point major) otherwise.  Returns after the stream has
  * synchronized.  On error the state stays at step n-1.  st may be NULL. */
 int nm_newmark_step(nm_ctx* ctx, const double* U_n, int per_point, nm_step_stats* st);
+
+/* The explicit central-difference scheme of section 2.3 (a context created with
+ * pb->beta == 0 and pb->gamma_nm == 0.5; FP64; route AUTO or PROJECTED).  Each step
+ * (eq. Central_diff_rule with eqs. b_explicit and Explicit_linear_momentum_arranged_3D):
+ *     u_n  = u_{n-1} + dt v_{n-1} + dt^2/2 a_{n-1}
+ *     v_b  = v_{n-1} + dt/2 a_{n-1} + dt/(2 rho) div(C : grad^s u_n)
+ *     f_n  = 2 rho / dt (Udot_n - v_b) on Gamma, 0 elsewhere
+ *     v_n  = v_b + dt/(2 rho) f_n    (so v_n = Udot_n on Gamma)
+ *     a_n  = (div(C : grad^s u_n) + f_n) / rho
+ * The velocity, not the displacement, is prescribed on Gamma.  Runs n_steps steps on the
+ * context stream and synchronizes once.  Udot (host) holds n_steps rows of dim values
+ * (uniform on Gamma, per_point == 0) or dim*n_gamma values (point major); row k is
+ * Udot(t_{n+k+1}).  nm_get_state's F_gamma is f of the last step.  The scheme is stable
+ * for dt <= 2 / omega_max (eq. Courant_stable; nm_omega2_max estimates omega_max^2); the
+ * library does not check dt.  st (may be NULL) receives the mean wall time per step.
+ * NM_EINVAL on a context of the implicit scheme or n_steps < 1; NM_ENAN on a non-finite
+ * velocity (the state is then unchanged). */
+int nm_explicit_step(nm_ctx* ctx, const double* Udot, int per_point, int n_steps, nm_step_stats* st);
+
+/* Largest eigenvalue omega^2 of the discrete problem K x = omega^2 rho x with
+ * K = -div(C : grad^s .) (section 2.3.3: "solving the discrete eigenvalue problem" for
+ * a heterogeneous medium), by power iteration on rho^-1 K.  x_dev: device FP64 3 x N start
+ * vector, overwritten by the last iterate (unit rho-weighted norm).  *omega2 receives the
+ * Rayleigh quotient x.Kx / x.rho x after `iters` products (a lower bound of omega_max^2 that
+ * approaches it as iters grows).  Any context; synchronous. */
+int nm_omega2_max(nm_ctx* ctx, void* x_dev, int iters, double* omega2);
 
 /* Au = A(u), eq. (Fourier_ND_A) mapped to real space, unscaled, no Gamma
  * projection.  u_dev / Au_dev: caller-owned device buffers of 3 x N values of

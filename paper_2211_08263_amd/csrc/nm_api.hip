@@ -78,6 +78,12 @@ struct nm_ctx {
     bool sfeat_ready = false;  // sfeat was written by the last fused corrector
     double* gbuf = nullptr; // dim * max(ng, 1)
     std::vector<double> G, LU, F_last;
+    // explicit central-difference scheme (beta == 0)
+    bool explicit_scheme = false;
+    double* Fdev = nullptr;      // dim * max(ng, 1): the Gamma force of the last explicit step
+    bool F_on_device = false;    // F_last is stale; Fdev holds the force
+    double* ubatch = nullptr;    // prescribed velocities of a batch of explicit steps
+    size_t ubatch_cap = 0;
     std::vector<int> piv;
     int64_t step = 0;
     std::string err;
@@ -184,7 +190,10 @@ XInvArgs xi_args(nm_ctx* c, void* spec, void* out, const void* aux, const void* 
 }
 
 // The six passes of q = A p after the x-forward one (which left the x spectrum of p in S).
-template <typename T> int chain_operator_rest(nm_ctx* c, const XInvArgs& ia)
+// xmode: the fused stage of the last pass; bdt2 (when not NaN) replaces beta dt^2 in the
+// scale -beta dt^2 of the divergence, so that the chain yields -bdt2 div sigma (+ rho p).
+template <typename T>
+int chain_operator_rest(nm_ctx* c, const XInvArgs& ia, int xmode = XI_OPERATOR, double bdt2 = NAN)
 {
     hipStream_t s = c->stream;
     void* spec = Prec<T>::spec(c);
@@ -193,12 +202,13 @@ template <typename T> int chain_operator_rest(nm_ctx* c, const XInvArgs& ia)
     const SpecLayout& lay = ia.lay;
     SpecParams sp = c->sp;
     sp.stop = lay.stop;
+    if (!std::isnan(bdt2)) sp.bdt2 = bdt2;
     LCHK(c, launch_colop<T>(YOP_DERIV, sp, lay, spec, spec2, tw, s));
     LCHK(c, launch_colop<T>(ZOP_STRAIN, sp, lay, spec, spec2, tw, s));
     LCHK(c, launch_xstress<T>(c->n1, spec2, lay, c->phase, Prec<T>::C(c), tw, s));
     LCHK(c, launch_colop<T>(YOP_DIV, sp, lay, spec, spec2, tw, s));
     LCHK(c, launch_colop<T>(ZOP_DIVZ, sp, lay, spec, spec2, tw, s));
-    LCHK(c, launch_xinv<T>(XI_OPERATOR, c->n1, ia, tw, s));
+    LCHK(c, launch_xinv<T>(xmode, c->n1, ia, tw, s));
     return NM_OK;
 }
 
@@ -253,6 +263,16 @@ template <typename T> int apply_A(nm_ctx* c, const T* x, T* out, const uint8_t* 
     fa.src = x;
     XInvArgs ia = xi_args(c, Prec<T>::spec(c), out, x, Prec<T>::rho(c), mask, nullptr);
     return chain_operator<T>(c, XF_PLAIN, fa, ia);
+}
+
+// out = scale * div(C : grad^s x) (FP64, no inertia term, no Gamma projection).
+int div_stress(nm_ctx* c, const double* x, double* out, double scale)
+{
+    XFwdArgs fa = xf_args(c, c->spec64);
+    fa.src = x;
+    XInvArgs ia = xi_args(c, c->spec64, out, x, c->rho64, nullptr, nullptr);
+    LCHK(c, launch_xfwd<double>(XF_PLAIN, c->n1, fa, c->tw64, c->stream));
+    return chain_operator_rest<double>(c, ia, XI_PLAIN, -scale);
 }
 
 int read_scalars(nm_ctx* c)
@@ -796,10 +816,15 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     if (pb->n_phases < 1 || pb->n_phases > 65536) return fail(c, NM_EINVAL, "n_phases out of range");
     c->nph = pb->n_phases;
     if (!pb->phase_id || !pb->C_voigt || !pb->rho) return fail(c, NM_EINVAL, "null material arrays");
-    if (!(pb->dt > 0) || !(pb->beta > 0) || !std::isfinite(pb->dt)) return fail(c, NM_EINVAL, "bad dt or beta");
+    if (!(pb->dt > 0) || !(pb->beta >= 0) || !std::isfinite(pb->dt) || !std::isfinite(pb->beta))
+        return fail(c, NM_EINVAL, "bad dt or beta");
     c->dt = pb->dt;
     c->beta = pb->beta;
     c->gam = pb->gamma_nm;
+    // beta = 0 with gamma = 1/2 is the explicit central-difference scheme (section 2.3)
+    c->explicit_scheme = pb->beta == 0.0;
+    if (c->explicit_scheme && pb->gamma_nm != 0.5)
+        return fail(c, NM_EUNSUPPORTED, "beta = 0 selects the central-difference scheme, which needs gamma = 1/2");
     if (pb->n_gamma < 0 || (pb->n_gamma > 0 && !pb->gamma_idx)) return fail(c, NM_EINVAL, "bad Gamma set");
     c->ng = pb->n_gamma;
     c->gidx_h.assign(pb->gamma_idx, pb->gamma_idx + c->ng);
@@ -809,6 +834,13 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
             return fail(c, NM_EINVAL, "Gamma indices must be sorted and unique");
     }
     c->opt = *op;
+    if (c->explicit_scheme) {
+        if (c->opt.precision != NM_PREC_FP64) return fail(c, NM_EUNSUPPORTED, "the explicit scheme runs in FP64");
+        if (c->opt.route == NM_ROUTE_GREEN)
+            return fail(c, NM_EUNSUPPORTED, "the explicit scheme prescribes the Gamma velocity directly (no Green route)");
+        c->opt.tol = c->opt.tol > 0 ? c->opt.tol : 1e-8;
+        c->opt.max_iter = c->opt.max_iter > 0 ? c->opt.max_iter : 1;
+    }
     if (!(c->opt.tol > 0) || c->opt.max_iter <= 0) return fail(c, NM_EINVAL, "tol and max_iter must be positive");
     if (c->opt.precision == NM_PREC_MIXED) {
         if (!(c->opt.inner_tol > 0)) c->opt.inner_tol = 1e-5;
@@ -905,20 +937,26 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     CHK(dalloc(c, &c->part_a, c->npart));
     CHK(dalloc(c, &c->winc, vec_blocks(3 * c->N)));
     CHK(dalloc(c, &c->part_b, c->npart));
-    // fields
-    double** f64[] = {&c->u, &c->v, &c->a, &c->ut, &c->b, &c->w, &c->r, &c->z, &c->p, &c->q};
-    for (double** f : f64) {
-        CHK(dalloc(c, f, n));
-        LCHK(c, launch_fill<double>(*f, 0.0, n, s));
+    // fields (the explicit scheme keeps only the state and one work field)
+    double** f64[] = {&c->u, &c->v, &c->a, &c->q, &c->ut, &c->b, &c->w, &c->r, &c->z, &c->p};
+    const int nf64 = c->explicit_scheme ? 4 : 10;
+    for (int k = 0; k < nf64; k++) {
+        CHK(dalloc(c, f64[k], n));
+        LCHK(c, launch_fill<double>(*f64[k], 0.0, n, s));
     }
     CHK(dalloc(c, &c->spec64, 6 * c->lay.cs));
     CHK(dalloc(c, &c->spec64b, 6 * c->lay.cs));
-    if (c->route == NM_ROUTE_GREEN) {
+    if (c->route == NM_ROUTE_GREEN && !c->explicit_scheme) {
         CHK(dalloc(c, &c->uf, n));
         LCHK(c, launch_fill<double>(c->uf, 0.0, n, s));
     }
-    CHK(dalloc(c, &c->spec32, 6 * c->lay.cs));
-    CHK(dalloc(c, &c->spec32b, 6 * c->lay.cs));
+    if (!c->explicit_scheme) {
+        CHK(dalloc(c, &c->spec32, 6 * c->lay.cs));
+        CHK(dalloc(c, &c->spec32b, 6 * c->lay.cs));
+    } else {
+        CHK(dalloc(c, &c->Fdev, c->dim * std::max<long>(c->ng, 1)));
+        LCHK(c, launch_fill<double>(c->Fdev, 0.0, c->dim * std::max<long>(c->ng, 1), s));
+    }
     if (c->opt.precision == NM_PREC_MIXED) {
         float** f32[] = {&c->d32, &c->r32, &c->p32, &c->q32};
         for (float** f : f32) {
@@ -934,13 +972,17 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     HIPCHK(c, hipStreamSynchronize(s));
     if (pb->u0) HIPCHK(c, hipMemcpy(c->u, pb->u0, c->dim * c->N * sizeof(double), hipMemcpyHostToDevice));
     if (pb->v0) HIPCHK(c, hipMemcpy(c->v, pb->v0, c->dim * c->N * sizeof(double), hipMemcpyHostToDevice));
-    if (pb->u0) {
+    if (pb->u0 && c->explicit_scheme) {
+        // a0 = div(C : grad^s u0) / rho
+        CHK(div_stress(c, c->u, c->q, 1.0));
+        LCHK(c, launch_div_rho(c->a, c->q, c->phase, c->rho64, c->N, s));
+    } else if (pb->u0) {
         // a0 = div(C : grad^s u0) / rho
         CHK(apply_A<double>(c, c->u, c->q, nullptr));
         LCHK(c, launch_accel0(c->a, c->u, c->q, c->phase, c->rho64, c->N, 3, c->sp.bdt2, s));
     }
-    if (c->route == NM_ROUTE_GREEN && c->ng > 0) CHK(build_green(c));
-    if (c->route == NM_ROUTE_PROJECTED && c->ng > 0) CHK(build_lift(c));
+    if (c->route == NM_ROUTE_GREEN && c->ng > 0 && !c->explicit_scheme) CHK(build_green(c));
+    if (c->route == NM_ROUTE_PROJECTED && c->ng > 0 && !c->explicit_scheme) CHK(build_lift(c));
     HIPCHK(c, hipStreamSynchronize(s));
     return NM_OK;
 }
@@ -1135,7 +1177,101 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
 int nm_newmark_step(nm_ctx* c, const double* U_n, int per_point, nm_step_stats* st)
 {
     if (!c) return NM_EINVAL;
+    if (c->explicit_scheme)
+        return fail(c, NM_EINVAL, "this context runs the explicit scheme (beta = 0): call nm_explicit_step");
     return step_impl(c, U_n, per_point, st);
+}
+
+// n_steps central-difference steps (section 2.3) without a host round trip in between.
+static int explicit_impl(nm_ctx* c, const double* Udot, int per_point, int n_steps, nm_step_stats* st)
+{
+    hipStream_t s = c->stream;
+    const int d = c->dim;
+    const long row = c->ng > 0 ? (per_point ? (long)d * c->ng : d) : 0;
+    const size_t total = (size_t)row * n_steps;
+    if (c->ng > 0) {
+        if (!Udot) return fail(c, NM_EINVAL, "null prescribed velocity");
+        for (size_t i = 0; i < total; i++)
+            if (!std::isfinite(Udot[i])) return fail(c, NM_ENAN, "non-finite prescribed velocity");
+        if (total > c->ubatch_cap) {
+            // grown on demand; released with the context
+            double* nb = nullptr;
+            CHK(dalloc(c, &nb, total));
+            c->ubatch = nb;
+            c->ubatch_cap = total;
+        }
+        HIPCHK(c, hipMemcpyAsync(c->ubatch, Udot, total * sizeof(double), hipMemcpyHostToDevice, s));
+    }
+    auto t0 = std::chrono::steady_clock::now();
+    const double dt = c->dt;
+    for (int k = 0; k < n_steps; k++) {
+        // u_n = u + dt v + dt^2/2 a, and its x spectrum
+        XFwdArgs fa = xf_args(c, c->spec64);
+        fa.u = c->u;
+        fa.v = c->v;
+        fa.a = c->a;
+        fa.dt = dt;
+        LCHK(c, launch_xfwd<double>(XF_EXPLICIT, c->n1, fa, c->tw64, s));
+        // (dt/2) div sigma(u_n) -> v <- v + dt/2 a + (dt/2) div sigma / rho, a <- div sigma / rho
+        XInvArgs ia = xi_args(c, c->spec64, nullptr, nullptr, c->rho64, nullptr, nullptr);
+        ia.p = c->v;
+        ia.x = c->a;
+        ia.dt = dt;
+        CHK(chain_operator_rest<double>(c, ia, XI_EXPLICIT, -0.5 * dt));
+        // Gamma: the force that gives the prescribed velocity
+        if (c->ng > 0)
+            LCHK(c, launch_explicit_gamma(c->v, c->a, c->phase, c->rho64, c->gidx, c->ng, c->ubatch + (size_t)row * k,
+                                          per_point, d, c->N, dt, c->Fdev, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    c->step += n_steps;
+    c->F_on_device = c->ng > 0;
+    if (st) {
+        nm_step_stats local{};
+        local.t_step_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count() / n_steps;
+        *st = local;
+    }
+    return NM_OK;
+}
+
+int nm_explicit_step(nm_ctx* c, const double* Udot, int per_point, int n_steps, nm_step_stats* st)
+{
+    if (!c) return NM_EINVAL;
+    if (!c->explicit_scheme)
+        return fail(c, NM_EINVAL, "nm_explicit_step needs a context created with beta = 0 (central differences)");
+    if (n_steps < 1) return fail(c, NM_EINVAL, "n_steps must be positive");
+    return explicit_impl(c, Udot, per_point, n_steps, st);
+}
+
+int nm_omega2_max(nm_ctx* c, void* x_dev, int iters, double* omega2)
+{
+    if (!c) return NM_EINVAL;
+    if (!x_dev || iters < 0 || !omega2) return fail(c, NM_EINVAL, "bad arguments");
+    hipStream_t s = c->stream;
+    double* x = (double*)x_dev;
+    double* y = c->q;
+    const long n = 3 * c->N;
+    c->pred_ready = false; // the work field q is shared with the step
+    double lam = 0.0;
+    for (int it = 0; it <= iters; it++) {
+        // x <- x / |x|_rho
+        LCHK(c, launch_rho_norm2(x, c->phase, c->rho64, c->N, c->part_a, s));
+        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_SLOT, 6, s));
+        CHK(read_scalars(c));
+        const double m = c->hscal[6];
+        if (!(m > 0) || !std::isfinite(m)) return fail(c, NM_ENAN, "start vector has no rho-weighted norm");
+        LCHK(c, launch_axpby<double>(x, x, x, 1.0 / std::sqrt(m) - 1.0, n, s));
+        // y = K x = -div sigma(x) ; lam = x . y
+        CHK(div_stress(c, x, y, -1.0));
+        CHK(dot64(c, x, y, &lam));
+        if (it == iters) break;
+        // x <- rho^-1 K x
+        LCHK(c, launch_div_rho(x, y, c->phase, c->rho64, c->N, s));
+    }
+    HIPCHK(c, hipStreamSynchronize(s));
+    *omega2 = lam;
+    return NM_OK;
 }
 
 int nm_apply_operator(nm_ctx* c, const void* u_dev, void* Au_dev, int dtype)
@@ -1143,6 +1279,7 @@ int nm_apply_operator(nm_ctx* c, const void* u_dev, void* Au_dev, int dtype)
     if (!c) return NM_EINVAL;
     if (!u_dev || !Au_dev || u_dev == Au_dev) return fail(c, NM_EINVAL, "bad buffers");
     if (dtype == NM_FP64) return apply_A<double>(c, (const double*)u_dev, (double*)Au_dev, nullptr);
+    if (dtype == NM_FP32 && !c->spec32) return fail(c, NM_EINVAL, "FP32 buffers are not held by an explicit context");
     if (dtype == NM_FP32) return apply_A<float>(c, (const float*)u_dev, (float*)Au_dev, nullptr);
     return fail(c, NM_EINVAL, "dtype must be NM_FP64 or NM_FP32");
 }
@@ -1150,6 +1287,7 @@ int nm_apply_operator(nm_ctx* c, const void* u_dev, void* Au_dev, int dtype)
 int nm_precond_apply(nm_ctx* c, const void* r_dev, void* z_dev, int dtype)
 {
     if (!c) return NM_EINVAL;
+    if (c->explicit_scheme) return fail(c, NM_EINVAL, "the explicit scheme has no preconditioner");
     if (!r_dev || !z_dev || r_dev == z_dev) return fail(c, NM_EINVAL, "bad buffers");
     if (dtype == NM_FP64) return precond_impl<double>(c, (const double*)r_dev, (double*)z_dev);
     if (dtype == NM_FP32) return precond_impl<float>(c, (const float*)r_dev, (float*)z_dev);
@@ -1160,6 +1298,7 @@ int nm_pcg_solve(nm_ctx* c, const void* b_dev, void* x_dev, int masked, double t
                  int* iters, double* relres)
 {
     if (!c) return NM_EINVAL;
+    if (c->explicit_scheme) return fail(c, NM_EINVAL, "the explicit scheme has no Krylov solver");
     if (!b_dev || !x_dev || b_dev == x_dev) return fail(c, NM_EINVAL, "bad buffers");
     if (!(tol > 0) || max_iter <= 0) return fail(c, NM_EINVAL, "bad tolerance or max_iter");
     double bref;
@@ -1188,6 +1327,10 @@ int nm_get_state(const nm_ctx* cc, double* u, double* v, double* a, double* F_ga
     if (!c) return NM_EINVAL;
     const size_t bytes = c->dim * c->N * sizeof(double);
     HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (c->F_on_device) {
+        HIPCHK(c, hipMemcpy(c->F_last.data(), c->Fdev, c->F_last.size() * sizeof(double), hipMemcpyDeviceToHost));
+        c->F_on_device = false;
+    }
     if (u) HIPCHK(c, hipMemcpy(u, c->u, bytes, hipMemcpyDeviceToHost));
     if (v) HIPCHK(c, hipMemcpy(v, c->v, bytes, hipMemcpyDeviceToHost));
     if (a) HIPCHK(c, hipMemcpy(a, c->a, bytes, hipMemcpyDeviceToHost));
@@ -1225,6 +1368,8 @@ int nm_profile_passes(nm_ctx* c, int which, const void* u_dev, void* out_dev, in
     if (!c) return NM_EINVAL;
     if (!u_dev || !out_dev || u_dev == out_dev || !ms || reps <= 0 || (which != 0 && which != 1))
         return fail(c, NM_EINVAL, "bad arguments");
+    if (c->explicit_scheme && (which == 1 || dtype != NM_FP64))
+        return fail(c, NM_EINVAL, "an explicit context profiles the FP64 operator only");
     if (dtype == NM_FP64) return profile_impl<double>(c, which, (const double*)u_dev, (double*)out_dev, reps, ms);
     if (dtype == NM_FP32) return profile_impl<float>(c, which, (const float*)u_dev, (float*)out_dev, reps, ms);
     return fail(c, NM_EINVAL, "dtype must be NM_FP64 or NM_FP32");
@@ -1233,6 +1378,7 @@ int nm_profile_passes(nm_ctx* c, int which, const void* u_dev, void* out_dev, in
 int nm_ws_attach(nm_ctx* c, nm_net* net)
 {
     if (!c) return NM_EINVAL;
+    if (c->explicit_scheme && net) return fail(c, NM_EINVAL, "the explicit scheme has no initial iterate to predict");
     if (net != c->net) c->l0mat_version = 0; // versions of different networks are unrelated
     c->net = net;
     if (!net || c->feat) return NM_OK;

@@ -40,9 +40,14 @@ struct SpecLayout {
 // Fused stage in front of the x-direction real-to-complex transform.
 // XF_UPDATE: r -= alpha q with the partial sums of r.r (the direction update is fused into
 // the preconditioner's last pass instead, launch_xpupdate).
-enum XFwdMode { XF_PLAIN = 0, XF_UPDATE = 2 };
+// XF_EXPLICIT: the displacement update u <- u + dt v + dt^2/2 a of the central-difference
+// scheme (written back to u) before the transform.
+enum XFwdMode { XF_PLAIN = 0, XF_UPDATE = 2, XF_EXPLICIT = 3 };
 // Fused stage after the x-direction complex-to-real transform.
-enum XInvMode { XI_PLAIN = 0, XI_OPERATOR = 1, XI_PRECOND = 2 };
+// XI_EXPLICIT: with o = (dt/2) div sigma from the transform, v <- v + dt/2 a + o/rho and
+// a <- 2 o / (dt rho) (central-difference velocity before the Gamma force; eq.
+// Explicit_linear_momentum_arranged_3D).
+enum XInvMode { XI_PLAIN = 0, XI_OPERATOR = 1, XI_PRECOND = 2, XI_EXPLICIT = 3 };
 // Axis-wise derivative stages of the operator on x-spectral (kx, y, z) data:
 //   YOP_DERIV : S[3+j] = D_y S[j], j < 3
 //   ZOP_STRAIN: S2 = Voigt strain (eps11, eps22, eps33, g23, g13, g12) / n1 from
@@ -62,6 +67,10 @@ enum ScalarSlot {
 
 struct XFwdArgs {
     const void* src;      // XF_PLAIN: input field
+    void* u = nullptr;        // XF_EXPLICIT: displacement (in/out)
+    const void* v = nullptr;  // XF_EXPLICIT: velocity
+    const void* a = nullptr;  // XF_EXPLICIT: acceleration
+    double dt = 0.0;          // XF_EXPLICIT: time increment
     void* r;              // XF_UPDATE: r (in/out)
     const void* q;        // XF_UPDATE: q (in)
     const double* scal;   // device scalars
@@ -83,8 +92,9 @@ struct XInvArgs {
     long nlines;
     long lines_per_comp;  // n2 * n3
     int dim;
-    void* p = nullptr;            // launch_xpupdate: search direction (in/out)
-    void* x = nullptr;            // launch_xpupdate: iterate (in/out)
+    void* p = nullptr;            // launch_xpupdate: search direction (in/out); XI_EXPLICIT: velocity (in/out)
+    void* x = nullptr;            // launch_xpupdate: iterate (in/out); XI_EXPLICIT: acceleration (in/out)
+    double dt = 0.0;              // XI_EXPLICIT: time increment
     const double* scal = nullptr; // launch_xpupdate: device scalars (alpha, beta, first)
 };
 

@@ -141,6 +141,20 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
             const V* src = (const V*)a.src + off;
 #pragma unroll
             for (int m = 0; m < R; m++) v[m] = src[t + m * G];
+        } else if constexpr (MODE == XF_EXPLICIT) {
+            // u_n = u_{n-1} + dt v_{n-1} + dt^2/2 a_{n-1}   (eq. Central_diff_rule)
+            const T dt = (T)a.dt, h2 = (T)(0.5 * a.dt * a.dt);
+            V* u = (V*)a.u + off;
+            const V* vv = (const V*)a.v + off;
+            const V* aa = (const V*)a.a + off;
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const int i = t + m * G;
+                const V uo = u[i], vo = vv[i], ao = aa[i];
+                const V un = V{uo.x + dt * vo.x + h2 * ao.x, uo.y + dt * vo.y + h2 * ao.y};
+                u[i] = un;
+                v[m] = un;
+            }
         } else {
             // r -= alpha q and the partial sums of r.r
             const T alpha = (T)a.scal[S_ALPHA];
@@ -206,7 +220,19 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
     uint32_t ph[R];
     uint16_t mk[R];
     const long vline = line % a.lines_per_comp;
-    if constexpr (MODE != XI_PLAIN) {
+    V ao[R];
+    if constexpr (MODE == XI_EXPLICIT) {
+        const V* vp = (const V*)a.p + off;
+        const V* ap = (const V*)a.x + off;
+#pragma unroll
+        for (int m = 0; m < R; m++) {
+            const int n = t + m * G;
+            au[m] = valid ? vp[n] : V{0, 0};
+            ao[m] = valid ? ap[n] : V{0, 0};
+            ph[m] = valid ? ((const uint32_t*)a.phase)[vline * M + n] : 0u;
+            mk[m] = 0;
+        }
+    } else if constexpr (MODE != XI_PLAIN) {
         const V* aux = (const V*)a.aux + off;
 #pragma unroll
         for (int m = 0; m < R; m++) {
@@ -234,6 +260,27 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
         if constexpr (MODE == XI_PLAIN) {
 #pragma unroll
             for (int m = 0; m < R; m++) out[t + m * G] = v[m];
+        } else if constexpr (MODE == XI_EXPLICIT) {
+            // o = dt/2 div sigma: v <- v + dt/2 a + o / rho, a <- (2/dt) o / rho
+            const bool zero_comp = (a.dim == 2) && (line / a.lines_per_comp == 2);
+            const T* rho = (const T*)a.rho;
+            const T hdt = (T)(0.5 * a.dt), idt2 = (T)(2.0 / a.dt);
+            V* vp = (V*)a.p + off;
+            V* ap = (V*)a.x + off;
+#pragma unroll
+            for (int m = 0; m < R; m++) {
+                const int n = t + m * G;
+                const T r0 = rho[ph[m] & 0xffffu], r1 = rho[ph[m] >> 16];
+                const V o = v[m];
+                V vn = V{au[m].x + hdt * ao[m].x + o.x / r0, au[m].y + hdt * ao[m].y + o.y / r1};
+                V an = V{idt2 * o.x / r0, idt2 * o.y / r1};
+                if (zero_comp) {
+                    vn = V{0, 0};
+                    an = V{0, 0};
+                }
+                vp[n] = vn;
+                ap[n] = an;
+            }
         } else {
             const bool zero_comp = (a.dim == 2) && (line / a.lines_per_comp == 2);
             const T* rho = (const T*)a.rho;
@@ -253,7 +300,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
             }
         }
     }
-    if constexpr (MODE != XI_PLAIN) {
+    if constexpr (MODE != XI_PLAIN && MODE != XI_EXPLICIT) {
         double s = block_sum256(part);
         if (threadIdx.x == 0 && a.partials) a.partials[blockIdx.x] = s;
     }
@@ -991,6 +1038,8 @@ template <typename T> int launch_xfwd(int mode, int n1, const XFwdArgs& a, const
     NM_SIZE_SWITCH(n1, {
         constexpr int M = NN / 2, R = (M >= 8 ? 8 : M);
         if (mode == XF_PLAIN) hipLaunchKernelGGL((k_xfwd<T, NN, R, XF_PLAIN>), dim3(blocks), dim3(kBlock), 0, s, a, t);
+        else if (mode == XF_EXPLICIT)
+            hipLaunchKernelGGL((k_xfwd<T, NN, R, XF_EXPLICIT>), dim3(blocks), dim3(kBlock), 0, s, a, t);
         else hipLaunchKernelGGL((k_xfwd<T, NN, R, XF_UPDATE>), dim3(blocks), dim3(kBlock), 0, s, a, t);
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -1005,6 +1054,8 @@ template <typename T> int launch_xinv(int mode, int n1, const XInvArgs& a, const
         if (mode == XI_PLAIN) hipLaunchKernelGGL((k_xinv<T, NN, R, XI_PLAIN>), dim3(blocks), dim3(kBlock), 0, s, a, t);
         else if (mode == XI_OPERATOR)
             hipLaunchKernelGGL((k_xinv<T, NN, R, XI_OPERATOR>), dim3(blocks), dim3(kBlock), 0, s, a, t);
+        else if (mode == XI_EXPLICIT)
+            hipLaunchKernelGGL((k_xinv<T, NN, R, XI_EXPLICIT>), dim3(blocks), dim3(kBlock), 0, s, a, t);
         else hipLaunchKernelGGL((k_xinv<T, NN, R, XI_PRECOND>), dim3(blocks), dim3(kBlock), 0, s, a, t);
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;

@@ -70,6 +70,17 @@ int launch_corrector_predictor(const double* un, double* ut, double* v, double* 
 // Initial acceleration from q = A u0: a0 = (rho u0 - q) / (beta dt^2 rho) = div(C : grad^s u0) / rho
 int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* phase, const double* rho, long N,
                   int ncomp, double bdt2, hipStream_t s);
+// Explicit central-difference scheme, Gamma voxels after the velocity pass: with vb = v there,
+// f = 2 rho / dt (Udot - vb), v = Udot, a += f / rho, F[dim*p + j] = f (eq.
+// Explicit_linear_momentum_arranged_3D and the force that prescribes the velocity).
+// Udot: dim values (uniform) or dim*ng values (per point).
+int launch_explicit_gamma(double* v, double* a, const uint16_t* phase, const double* rho, const int64_t* gidx, long ng,
+                          const double* Udot, int per_point, int dim, long N, double dt, double* F, hipStream_t s);
+// Partial sums of sum rho(phase) x^2 over a 3 x N field (vec_blocks(3 N) of them).
+int launch_rho_norm2(const double* x, const uint16_t* phase, const double* rho, long N, double* partials,
+                     hipStream_t s);
+// x = y / rho(phase) for 3 x N fields.
+int launch_div_rho(double* x, const double* y, const uint16_t* phase, const double* rho, long N, hipStream_t s);
 // Second-order Taylor start: x = u + dt v + dt^2/2 a
 int launch_taylor(double* x, const double* u, const double* v, const double* a, long n, double dt, hipStream_t s);
 

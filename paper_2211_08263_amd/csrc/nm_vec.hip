@@ -469,6 +469,68 @@ int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* 
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
+__global__ __launch_bounds__(kBlock) void k_explicit_gamma(double* __restrict__ v, double* __restrict__ a,
+                                                          const uint16_t* __restrict__ phase,
+                                                          const double* __restrict__ rho,
+                                                          const int64_t* __restrict__ gidx, long ng,
+                                                          const double* __restrict__ Udot, int per_point, int dim,
+                                                          long N, double dt, double* __restrict__ F)
+{
+    const long e = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= ng * dim) return;
+    const long p = e / dim;
+    const int j = (int)(e % dim);
+    const long g = gidx[p];
+    const long i = j * N + g;
+    const double r = rho[phase[g]];
+    const double U = per_point ? Udot[dim * p + j] : Udot[j];
+    const double f = 2.0 * r / dt * (U - v[i]);
+    v[i] = U;
+    a[i] = a[i] + f / r;
+    F[dim * p + j] = f;
+}
+int launch_explicit_gamma(double* v, double* a, const uint16_t* phase, const double* rho, const int64_t* gidx, long ng,
+                          const double* Udot, int per_point, int dim, long N, double dt, double* F, hipStream_t s)
+{
+    const long n = ng * dim;
+    if (n == 0) return 0;
+    hipLaunchKernelGGL(k_explicit_gamma, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, v, a, phase,
+                       rho, gidx, ng, Udot, per_point, dim, N, dt, F);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rho_norm2(const double* __restrict__ x, const uint16_t* __restrict__ phase,
+                                                     const double* __restrict__ rho, long N, long n,
+                                                     double* __restrict__ partials)
+{
+    double acc = 0.0;
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        acc += rho[phase[i % N]] * x[i] * x[i];
+    const double s = block_sum_v(acc);
+    if (threadIdx.x == 0) partials[blockIdx.x] = s;
+}
+int launch_rho_norm2(const double* x, const uint16_t* phase, const double* rho, long N, double* partials,
+                     hipStream_t s)
+{
+    const long n = 3 * N;
+    hipLaunchKernelGGL(k_rho_norm2, dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, phase, rho, N, n, partials);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_div_rho(double* __restrict__ x, const double* __restrict__ y,
+                                                   const uint16_t* __restrict__ phase, const double* __restrict__ rho,
+                                                   long N, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x)
+        x[i] = y[i] / rho[phase[i % N]];
+}
+int launch_div_rho(double* x, const double* y, const uint16_t* phase, const double* rho, long N, hipStream_t s)
+{
+    const long n = 3 * N;
+    hipLaunchKernelGGL(k_div_rho, dim3(vec_blocks(n)), dim3(kBlock), 0, s, x, y, phase, rho, N, n);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 __global__ __launch_bounds__(kBlock) void k_taylor(double* x, const double* u, const double* v, const double* a, long n,
                                                    double dt)
 {

@@ -37,7 +37,7 @@ EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_preco
             "nm_net_forward", "nm_net_train_step", "nm_net_gradients", "nm_conv3d_bf16", "nm_conv3d_bf16_noalloc",
             "nm_ws_attach",
             "nm_ws_features", "nm_ws_target", "nm_ws_predict", "nm_ws_residual_sample", "nm_ws_train_residual",
-            "nm_last_error", "nm_destroy")
+            "nm_explicit_step", "nm_omega2_max", "nm_last_error", "nm_destroy")
 
 
 class NewmarkError(RuntimeError):
@@ -128,6 +128,8 @@ def load_library():
                                         C.POINTER(C.c_double)]
     L.nm_ws_train_residual.argtypes = [vp, vp, vp, C.c_double, C.c_double, C.c_int, C.c_float,
                                        C.POINTER(C.c_float)]
+    L.nm_explicit_step.argtypes = [vp, vp, i, i, C.POINTER(StepStats)]
+    L.nm_omega2_max.argtypes = [vp, vp, i, C.POINTER(C.c_double)]
     L.nm_get_stream.argtypes = [vp]
     L.nm_get_stream.restype = vp
     L.nm_last_error.argtypes = [vp]
@@ -238,6 +240,26 @@ def newmark_step(ctx: Context, U, per_point: bool = False) -> dict:
     st = StepStats()
     ctx.check(load_library().nm_newmark_step(ctx.handle, Ua.ctypes.data, int(bool(per_point)), C.byref(st)))
     return st.as_dict()
+
+
+def explicit_step(ctx: Context, Udot, per_point: bool = False, n_steps: int = 1) -> dict:
+    """n_steps central-difference steps; Udot holds n_steps rows of prescribed velocities."""
+    Ua = _c64(Udot).reshape(-1)
+    st = StepStats()
+    ctx.check(load_library().nm_explicit_step(ctx.handle, Ua.ctypes.data if Ua.size else None, int(bool(per_point)),
+                                              int(n_steps), C.byref(st)))
+    return st.as_dict()
+
+
+def omega2_max(ctx: Context, x, iters: int) -> float:
+    """Power-iteration estimate of omega_max^2 (x: device float64 tensor of 3 x N, overwritten)."""
+    _check_field(ctx, x)
+    import torch
+    if x.dtype != torch.float64:
+        raise TypeError("float64 start vector expected")
+    w = C.c_double(0)
+    ctx.check(load_library().nm_omega2_max(ctx.handle, x.data_ptr(), int(iters), C.byref(w)))
+    return w.value
 
 
 def _dtype_code(t):
