@@ -448,6 +448,103 @@ def extrude_field(f: np.ndarray, n: int, axis: int) -> np.ndarray:
     return np.ascontiguousarray(np.repeat(f, n, axis=3 - axis))
 
 
+# Table 1 of the paper (E in GPa, rho in kg/m^3, Poisson ratio); scaled below so that
+# aluminium has E = 1 and rho = 1.
+TABLE1 = {"Al": (70.3, 2700.0, 0.345), "Fe": (211.4, 7850.0, 0.293), "U": (172.0, 18950.0, 0.3)}
+
+
+def table1_scaled(name: str):
+    """(21 Voigt constants, density) of a Table 1 metal, isotropic, scaled by aluminium."""
+    E, rho, nu = TABLE1[name]
+    E0, rho0, _ = TABLE1["Al"]
+    return voigt_to21(isotropic_voigt66(E / E0, nu)), rho / rho0
+
+
+def iso_speeds(c21: np.ndarray, rho: float):
+    """Longitudinal and shear speeds of an isotropic stiffness."""
+    C = voigt_from21(c21)
+    return math.sqrt(C[0, 0] / rho), math.sqrt(C[5, 5] / rho)
+
+
+def make_planar_bar(n1: int = 512, n2: int = 8, n3: int = 8, layers=(("Al", 1.0),), wave: str = "P",
+                    wavelength_vox: float = 64.0, cfl: float = 2.0, tol: float = 1e-10) -> Problem:
+    """Plane-wave bar of section 3.2: x-layered Table 1 metals (consecutive fractions of n1),
+    Gamma = the x = 0 plane, Ricker pulse along x (P wave) or y (S wave) with the given
+    wavelength in voxels at the first layer's speed; dt = cfl / (largest longitudinal speed)."""
+    mats = [table1_scaled(m) for m, _ in layers]
+    C = np.stack([m[0] for m in mats])
+    rho = np.array([m[1] for m in mats])
+    ends = np.cumsum([f for _, f in layers])
+    ends = ends / ends[-1]
+    xc = (np.arange(n1) + 0.5) / n1
+    lay = np.searchsorted(ends, xc, side="right").clip(0, len(layers) - 1).astype(np.uint16)
+    phase = np.ascontiguousarray(np.broadcast_to(lay[None, None, :], (n3, n2, n1)))
+    cL0, cS0 = iso_speeds(C[0], rho[0])
+    c_max = max(iso_speeds(C[g], rho[g])[0] for g in range(len(layers)))
+    dt = cfl / c_max
+    fc = (cL0 if wave == "P" else cS0) / wavelength_vox
+    pb = Problem(f"bar-{wave}", 3, (n1, n2, n3), (float(n1), float(n2), float(n3)), phase, C, rho,
+                 gamma_x_slab((n1, n2, n3)), dt, pulse_fc=fc, tol=tol,
+                 pulse_dir=(1.0, 0.0, 0.0) if wave == "P" else (0.0, 1.0, 0.0))
+    return pb
+
+
+def gamma_cylinder_x(n: Tuple[int, int, int], centre, radius: float) -> np.ndarray:
+    """Voxels whose (y, z) centre lies within radius of centre (every x): a source line
+    through an x-periodic plate."""
+    n1, n2, n3 = n
+    y = np.arange(n2) + 0.5
+    z = np.arange(n3) + 0.5
+    disc = ((y[None, :] - centre[0]) ** 2 + (z[:, None] - centre[1]) ** 2) <= radius * radius  # (n3, n2)
+    full = np.broadcast_to(disc[:, :, None], (n3, n2, n1))
+    return np.flatnonzero(full.ravel()).astype(np.int64)
+
+
+def make_plate(n: int = 512, n1: int = 8, radius: float = 2.5, framed: bool = False, wavelength_vox: float = 32.0,
+               cfl: float = 2.0, tol: float = 1e-8) -> Problem:
+    """Circular waves of section 4.1.1 (homogeneous Al plate) and 4.1.2 (Al core framed by Fe,
+    core side 0.39 of the plate): the plate is x-periodic and constant along x (n1 voxels, the
+    paper's one-voxel thickness), the source a cylinder of the given radius through the centre
+    of the (y, z) plane, prescribed along x (transverse to the plate: antiplane shear waves),
+    Ricker pulse with the given wavelength at aluminium's shear speed."""
+    al, fe = table1_scaled("Al"), table1_scaled("Fe")
+    C = np.stack([al[0], fe[0]])
+    rho = np.array([al[1], fe[1]])
+    phase = np.zeros((n, n, n1), np.uint16)
+    if framed:
+        yz = (np.arange(n) + 0.5) / n
+        core = np.abs(yz - 0.5) <= 0.39 / 2
+        inside = core[:, None] & core[None, :]  # (z, y)
+        phase[:] = np.where(inside, 0, 1).astype(np.uint16)[:, :, None]
+    c_max = max(iso_speeds(C[g], rho[g])[0] for g in range(2))
+    dt = cfl / c_max
+    fc = iso_speeds(al[0], al[1])[1] / wavelength_vox
+    g = gamma_cylinder_x((n1, n, n), (n / 2.0, n / 2.0), radius)
+    return Problem("plate-framed" if framed else "plate", 3, (n1, n, n), (float(n1), float(n), float(n)), phase, C, rho,
+                   g, dt, pulse_fc=fc, tol=tol)
+
+
+def make_sphere_source(n: int = 128, radius: float = 2.0, framed: bool = False, wavelength_vox: float = 16.0,
+                       cfl: float = 2.0, tol: float = 1e-8) -> Problem:
+    """Spherical waves of section 4.1.3 (homogeneous Al cube) and 4.2 (Al cube of side 0.62
+    framed by Fe): Gamma = the voxels within radius of the centre, displacement along x,
+    Ricker pulse with the given wavelength at aluminium's shear speed."""
+    al, fe = table1_scaled("Al"), table1_scaled("Fe")
+    C = np.stack([al[0], fe[0]])
+    rho = np.array([al[1], fe[1]])
+    phase = np.zeros((n, n, n), np.uint16)
+    if framed:
+        c1 = np.abs((np.arange(n) + 0.5) / n - 0.5) <= 0.62 / 2
+        inside = c1[:, None, None] & c1[None, :, None] & c1[None, None, :]
+        phase = np.where(inside, 0, 1).astype(np.uint16)
+    c_max = max(iso_speeds(C[g], rho[g])[0] for g in range(2))
+    dt = cfl / c_max
+    fc = iso_speeds(al[0], al[1])[1] / wavelength_vox
+    g = gamma_sphere((n, n, n), (n / 2.0, n / 2.0, n / 2.0), radius)
+    return Problem("sphere-framed" if framed else "sphere", 3, (n, n, n), (float(n),) * 3, phase, C, rho, g, dt,
+                   pulse_fc=fc, tol=tol)
+
+
 def random_field(shape, seed: int, dtype=np.float64) -> np.ndarray:
     """i.i.d. N(0,1) field (operator micro-benchmark and parity input)."""
     return np.random.default_rng(seed).standard_normal(shape).astype(dtype)

@@ -294,3 +294,35 @@ def test_interface_transmission_amplitude():
     u = _run_1d(n, float(n), [E1, E2], [r1, r2], phase, dt, steps, lambda t: W.ricker(t, fc), x0)
     peak_t = u[-1][n // 2 + 8: n // 2 + n // 4].max()
     assert abs(peak_t - AT) / AT < 2e-2, (peak_t, AT)
+
+
+def test_nyquist_mode_carries_no_stiffness_on_even_grids():
+    """Reading of the Nyquist bin (frequency zero at k = N/2 on even grids): the checkerboard
+    mode (-1)^i has no stiffness, so a point source whose displacement has a non-zero time
+    integral (the paper's bell pulse of section 3.1) displaces it like a free mass across the
+    whole bar at once.  Ahead of both wave fronts, where d'Alembert's solution is zero, the
+    bar then holds a pure checkerboard (and the smooth field near the source is offset by the
+    same amount, so that the source point still follows U).  The paper's grids are odd and
+    have no such bin.  A Ricker pulse, whose displacement integrates to zero, leaves the mode
+    at rest once it has passed: the workloads and validation runs use it."""
+    n, L, c = 512, 512.0, 1.0
+    T = 0.2 * n / c
+    omega = np.pi / T
+    t_end = T + 0.25 * n / c
+    steps = 230
+    dt = t_end / steps
+    x = np.arange(n) + 0.5
+    d = np.minimum(np.abs(x - 0.5), L - np.abs(x - 0.5))
+    u = _run_1d(n, L, [c * c], [1.0], np.zeros(n, np.uint16), dt, steps,
+                lambda t: W.bell_pulse(t, 1.0, omega))[-1]
+    exact = W.bell_pulse(t_end - d / c, 1.0, omega)
+    chk = (-1.0) ** np.arange(n)
+    ahead = d > c * t_end + 4  # not reached by either front
+    assert ahead.sum() > 20 and np.abs(exact[ahead]).max() == 0.0
+    amp = float(np.mean(u[ahead] * chk[ahead]))
+    assert abs(amp) > 0.05, amp
+    assert np.abs(u[ahead] - amp * chk[ahead]).max() < 1e-3 * abs(amp)
+    # with the Ricker pulse the mode is back at rest after the pulse
+    fc = c / 64
+    u2 = _run_1d(n, L, [c * c], [1.0], np.zeros(n, np.uint16), 1.0, 300, lambda t: W.ricker(t, fc))[-1]
+    assert abs(float(np.dot(u2, chk) / n)) < 1e-3 * np.abs(u2).max()
