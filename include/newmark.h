@@ -87,12 +87,16 @@ typedef struct nm_options {
     int compute_reaction;     /* projected route: also compute F on Gamma (one extra operator apply) */
     int true_residual;        /* projected route: report the FP64 ||P(b - A u)|| / ||b_ref|| of the solution
                                  (one extra FP64 operator apply) instead of the solver's own estimate */
+    const double* green_in;   /* GREEN route: a stored Green matrix ((dim n_gamma)^2, row major, as
+                                 nm_green_matrix returns it for this problem and dt) to reuse instead of
+                                 the unit-force solves (section 3.2: the preprocessing of an RVE can be
+                                 stored and reused), or NULL; host, copied */
 } nm_options;
 
 typedef struct nm_step_stats {
     int iters[2];             /* FP64 solves: PCG iterations (Green route: u_b, u_f; projected: [0], [1] = 0) */
-    int sweeps;               /* mixed precision: FP64 refinement sweeps */
-    int inner_iters;          /* mixed precision: total FP32 PCG iterations */
+    int sweeps;               /* mixed precision: FP64 refinement sweeps (Green route: of both solves) */
+    int inner_iters;          /* mixed precision: total FP32 PCG iterations (Green route: of both solves) */
     double relres;            /* final relative residual: the FP64 residual of the solution when
                                  true_residual is set, else the value the stopping test used (the
                                  recursive residual; in mixed precision the last FP64 residual or
@@ -108,9 +112,10 @@ typedef struct nm_ctx nm_ctx;
  * central-difference scheme, see nm_explicit_step): copies the problem to the device, forms the reference
  * medium (volume averages of C and rho, eq. (precond)), the FFT twiddle
  * tables, the Gamma route (GREEN: d*n_gamma unit-force solves of eq.
- * (solve_green), the matrix G of eq. (G) and its LU factors) and the initial
- * acceleration a0 = div(C : grad^s u0) / rho.  hip_stream may be NULL (a
- * stream is created).  On success *out owns all resources. */
+ * (solve_green) in the context's precision, or a stored G from options->green_in,
+ * the matrix G of eq. (G) on the device and its LU factors with partial pivoting, also
+ * on the device) and the initial acceleration a0 = div(C : grad^s u0) / rho.  hip_stream
+ * may be NULL (a stream is created).  On success *out owns all resources. */
 int nm_newmark_init(const nm_problem* pb, const nm_options* op, void* hip_stream, nm_ctx** out);
 
 /* Advance one step: t_n = t_{n-1} + dt.  U_n (host) holds the prescribed
@@ -173,8 +178,13 @@ int nm_set_state(nm_ctx* ctx, const double* u, const double* v, const double* a,
  * step (steps swap the displacement buffers); writes through them are seen by the
  * next step. */
 int nm_state_device_ptrs(nm_ctx* ctx, void** u, void** v, void** a);
-/* The Green matrix (d*n_gamma)^2, row major, before factorization; GREEN route only. */
+/* The Green matrix (d*n_gamma)^2, row major, before factorization; GREEN route only.
+ * Stored and passed back through nm_options.green_in it replaces the unit-force solves. */
 int nm_green_matrix(const nm_ctx* ctx, double* G);
+/* X = G^-1 V (host vectors of d*n_gamma values) with the LU factors the context holds on
+ * the device (the solve of eq. L-determination_ND without the 1/(beta dt^2)); GREEN
+ * route only.  Synchronous. */
+int nm_green_solve(nm_ctx* ctx, const double* V, double* X);
 
 /* Measurement: run the passes of one operator apply (which == 0: seven passes)
  * or one preconditioner apply (which == 1: five passes) reps times on the

@@ -9,6 +9,7 @@
 #include "nm_passes.h"
 #include "nm_vec.h"
 #include "nm_net.h"
+#include "nm_green.h"
 
 #include <algorithm>
 #include <chrono>
@@ -77,14 +78,17 @@ struct nm_ctx {
     hipEvent_t ev_warm[2] = {nullptr, nullptr}; // brackets the learned start on the stream (timing only)
     bool sfeat_ready = false;  // sfeat was written by the last fused corrector
     double* gbuf = nullptr; // dim * max(ng, 1)
-    std::vector<double> G, LU, F_last;
+    std::vector<double> G, F_last; // G: host copy (row major) for nm_green_matrix
+    double* Gdev = nullptr;        // G, then its LU factors (column major, d n_gamma square)
+    int* pivdev = nullptr;         // row swaps of the factorization
+    int* singdev = nullptr;        // set by the factorization on a zero pivot
+    int green_sweeps = 0, green_inner = 0; // mixed-precision Green route: running totals
     // explicit central-difference scheme (beta == 0)
     bool explicit_scheme = false;
     double* Fdev = nullptr;      // dim * max(ng, 1): the Gamma force of the last explicit step
     bool F_on_device = false;    // F_last is stale; Fdev holds the force
     double* ubatch = nullptr;    // prescribed velocities of a batch of explicit steps
     size_t ubatch_cap = 0;
-    std::vector<int> piv;
     int64_t step = 0;
     std::string err;
     std::vector<void*> allocs;
@@ -554,84 +558,104 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
     return NM_OK;
 }
 
-// Dense LU with partial pivoting (host, row major); 0 or -1 on a zero pivot.
-int lu_factor(std::vector<double>& A, int n, std::vector<int>& piv)
+// Mixed precision without a Gamma projection (the Green route's solves): FP64 residual
+// r = rhs - A x, FP32 PCG correction, x += d, until ||r|| <= tol bref.
+int solve_mixed_plain(nm_ctx* c, const double* rhs, double* x, double bref, double tol, int* sweeps_out,
+                      int* inner_out)
 {
-    piv.resize(n);
-    for (int c = 0; c < n; c++) {
-        int pr = c;
-        double best = std::fabs(A[(size_t)c * n + c]);
-        for (int i = c + 1; i < n; i++) {
-            double v = std::fabs(A[(size_t)i * n + c]);
-            if (v > best) {
-                best = v;
-                pr = i;
-            }
-        }
-        piv[c] = pr;
-        if (best == 0.0) return -1;
-        if (pr != c)
-            for (int j = 0; j < n; j++) std::swap(A[(size_t)c * n + j], A[(size_t)pr * n + j]);
-        const double inv = 1.0 / A[(size_t)c * n + c];
-        for (int i = c + 1; i < n; i++) {
-            double* ri = &A[(size_t)i * n];
-            const double f = ri[c] * inv;
-            ri[c] = f;
-            if (f != 0.0) {
-                const double* rc = &A[(size_t)c * n];
-                for (int j = c + 1; j < n; j++) ri[j] -= f * rc[j];
-            }
-        }
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    if (bref <= 0) bref = 1.0;
+    int sweeps = 0, inner = 0;
+    for (;;) {
+        CHK(apply_A<double>(c, x, c->q, nullptr));
+        LCHK(c, launch_residual<double>(rhs, c->q, c->r, nullptr, c->N, 3, c->part_a, s, c->r32));
+        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+        CHK(read_scalars(c));
+        const double rr = c->hscal[S_RR];
+        if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual in refinement sweep %d", sweeps);
+        if (std::sqrt(rr) <= tol * bref) break;
+        if (sweeps >= c->opt.max_sweeps)
+            return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps (rel %.3g)", tol, sweeps,
+                        std::sqrt(rr) / bref);
+        LCHK(c, launch_fill<float>(c->d32, 0.0f, n, s));
+        PcgResult pr;
+        const double need = 0.5 * tol * bref / std::sqrt(rr);
+        CHK(pcg<float>(c, nullptr, c->d32, c->r32, c->p32, c->q32, false, true, std::sqrt(rr),
+                       need > c->opt.inner_tol ? need : c->opt.inner_tol, c->opt.max_iter, -1, true, &pr, rr, x));
+        inner += pr.iters;
+        sweeps++;
     }
-    return 0;
+    if (sweeps_out) *sweeps_out += sweeps;
+    if (inner_out) *inner_out += inner;
+    return NM_OK;
 }
 
-void lu_solve(const std::vector<double>& LU, int n, const std::vector<int>& piv, double* b)
+// One solve of the Green route (A x = rhs to tol relative to bref, no projection) in the
+// context's precision; mixed precision adds its sweeps and FP32 iterations to the
+// context's running totals.
+int green_solve(nm_ctx* c, const double* rhs, double* x, double bref, double tol, bool x_zero, PcgResult* res)
 {
-    for (int c = 0; c < n; c++)
-        if (piv[c] != c) std::swap(b[c], b[piv[c]]);
-    for (int i = 0; i < n; i++) {
-        double s = b[i];
-        for (int j = 0; j < i; j++) s -= LU[(size_t)i * n + j] * b[j];
-        b[i] = s;
+    if (c->opt.precision == NM_PREC_MIXED) {
+        *res = PcgResult{};
+        res->converged = true;
+        return solve_mixed_plain(c, rhs, x, bref, tol, &c->green_sweeps, &c->green_inner);
     }
-    for (int i = n - 1; i >= 0; i--) {
-        double s = b[i];
-        for (int j = i + 1; j < n; j++) s -= LU[(size_t)i * n + j] * b[j];
-        b[i] = s / LU[(size_t)i * n + i];
-    }
+    return pcg<double>(c, rhs, x, c->r, c->p, c->q, false, x_zero, bref, tol, c->opt.max_iter, -1, false, res);
 }
 
-// G from the unit-force solves of eq. (solve_green): column d p + j is the
-// Gamma trace of A^-1 (e_j at x_p); rows ordered d q + i.
-int build_green(nm_ctx* c)
+// G from the unit-force solves of eq. (solve_green): column d p + j is the Gamma trace of
+// A^-1 (e_j at x_p), rows ordered d q + i; written into the device matrix column by column
+// (no host round trip per column).  With a stored G (row major, as nm_green_matrix returns
+// it) the solves are skipped.  Then its LU factors on the device.
+int build_green(nm_ctx* c, const double* G_in)
 {
     hipStream_t s = c->stream;
     const int d = c->dim;
     const long n = 3 * c->N;
-    const int nd = (int)(d * c->ng);
+    const long nd = (long)d * c->ng;
+    CHK(dalloc(c, &c->Gdev, (size_t)nd * nd));
+    CHK(dalloc(c, &c->pivdev, nd));
+    CHK(dalloc(c, &c->singdev, 1));
     c->G.assign((size_t)nd * nd, 0.0);
-    std::vector<double> col(3 * c->ng);
-    double unit[3];
-    for (long pnt = 0; pnt < c->ng; pnt++)
-        for (int j = 0; j < d; j++) {
-            LCHK(c, launch_fill<double>(c->b, 0.0, n, s));
-            unit[0] = unit[1] = unit[2] = 0.0;
-            unit[j] = 1.0;
-            HIPCHK(c, hipMemcpyAsync(c->Ubuf, unit, 3 * sizeof(double), hipMemcpyHostToDevice, s));
-            LCHK(c, launch_set_gamma(c->b, c->gidx + pnt, 1, c->Ubuf, 0, 3, c->N, s));
-            LCHK(c, launch_fill<double>(c->w, 0.0, n, s));
-            PcgResult pr;
-            CHK(pcg<double>(c, c->b, c->w, c->r, c->p, c->q, false, true, 1.0, c->opt.green_tol,
-                            c->opt.max_iter, -1, false, &pr));
-            LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));
-            HIPCHK(c, hipMemcpyAsync(col.data(), c->gbuf, 3 * c->ng * sizeof(double), hipMemcpyDeviceToHost, s));
-            HIPCHK(c, hipStreamSynchronize(s));
-            for (long qq = 0; qq < c->ng; qq++)
-                for (int i = 0; i < d; i++) c->G[(size_t)(d * qq + i) * nd + (d * pnt + j)] = col[3 * qq + i];
-        }
-    c->LU = c->G;
-    if (lu_factor(c->LU, nd, c->piv) != 0) return fail(c, NM_ESINGULAR, "zero pivot in the Green matrix");
+    if (G_in) {
+        std::vector<double> cm((size_t)nd * nd); // column major on the device
+        for (long i = 0; i < nd; i++)
+            for (long j = 0; j < nd; j++) {
+                const double v = G_in[(size_t)i * nd + j];
+                if (!std::isfinite(v)) return fail(c, NM_EINVAL, "non-finite entry in the stored Green matrix");
+                cm[(size_t)j * nd + i] = v;
+            }
+        std::memcpy(c->G.data(), G_in, c->G.size() * sizeof(double));
+        HIPCHK(c, hipMemcpy(c->Gdev, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else {
+        double unit[3];
+        for (long pnt = 0; pnt < c->ng; pnt++)
+            for (int j = 0; j < d; j++) {
+                LCHK(c, launch_fill<double>(c->b, 0.0, n, s));
+                unit[0] = unit[1] = unit[2] = 0.0;
+                unit[j] = 1.0;
+                HIPCHK(c, hipMemcpyAsync(c->Ubuf, unit, 3 * sizeof(double), hipMemcpyHostToDevice, s));
+                LCHK(c, launch_set_gamma(c->b, c->gidx + pnt, 1, c->Ubuf, 0, 3, c->N, s));
+                LCHK(c, launch_fill<double>(c->w, 0.0, n, s));
+                PcgResult pr;
+                CHK(green_solve(c, c->b, c->w, 1.0, c->opt.green_tol, true, &pr));
+                LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));
+                LCHK(c, launch_green_column(c->Gdev, nd, d * pnt + j, c->gbuf, c->ng, d, s));
+                // unit is a stack buffer that the next copy overwrites
+                HIPCHK(c, hipStreamSynchronize(s));
+            }
+        std::vector<double> cm((size_t)nd * nd);
+        HIPCHK(c, hipMemcpy(cm.data(), c->Gdev, cm.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (long i = 0; i < nd; i++)
+            for (long j = 0; j < nd; j++) c->G[(size_t)i * nd + j] = cm[(size_t)j * nd + i];
+    }
+    LCHK(c, launch_fill<int>(c->singdev, 0, 1, s));
+    LCHK(c, lu_factor_device(c->Gdev, (int)nd, c->pivdev, c->singdev, s));
+    int sing = 0;
+    HIPCHK(c, hipMemcpyAsync(&sing, c->singdev, sizeof(int), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    if (sing) return fail(c, NM_ESINGULAR, "zero pivot in the Green matrix");
     return NM_OK;
 }
 
@@ -848,8 +872,6 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     }
     if (!(c->opt.green_tol > 0)) c->opt.green_tol = c->opt.tol * 1e-2;
     c->route = c->opt.route == NM_ROUTE_GREEN ? NM_ROUTE_GREEN : NM_ROUTE_PROJECTED;
-    if (c->route == NM_ROUTE_GREEN && c->opt.precision == NM_PREC_MIXED)
-        return fail(c, NM_EUNSUPPORTED, "mixed precision runs on the projected route");
     if (c->opt.warm_start < NM_WS_COLD || c->opt.warm_start > NM_WS_LEARNED)
         return fail(c, NM_EINVAL, "unknown warm start");
 
@@ -953,7 +975,8 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     if (!c->explicit_scheme) {
         CHK(dalloc(c, &c->spec32, 6 * c->lay.cs));
         CHK(dalloc(c, &c->spec32b, 6 * c->lay.cs));
-    } else {
+    }
+    if (c->explicit_scheme || c->route == NM_ROUTE_GREEN) {
         CHK(dalloc(c, &c->Fdev, c->dim * std::max<long>(c->ng, 1)));
         LCHK(c, launch_fill<double>(c->Fdev, 0.0, c->dim * std::max<long>(c->ng, 1), s));
     }
@@ -981,7 +1004,7 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
         CHK(apply_A<double>(c, c->u, c->q, nullptr));
         LCHK(c, launch_accel0(c->a, c->u, c->q, c->phase, c->rho64, c->N, 3, c->sp.bdt2, s));
     }
-    if (c->route == NM_ROUTE_GREEN && c->ng > 0 && !c->explicit_scheme) CHK(build_green(c));
+    if (c->route == NM_ROUTE_GREEN && c->ng > 0 && !c->explicit_scheme) CHK(build_green(c, op->green_in));
     if (c->route == NM_ROUTE_PROJECTED && c->ng > 0 && !c->explicit_scheme) CHK(build_lift(c));
     HIPCHK(c, hipStreamSynchronize(s));
     return NM_OK;
@@ -1073,38 +1096,29 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         double bn;
         CHK(norm2<double>(c, c->b, &bn));
         PcgResult r1, r2;
-        CHK(pcg<double>(c, c->b, c->w, c->r, c->p, c->q, false, false, std::sqrt(bn), c->opt.tol,
-                        c->opt.max_iter, -1, false, &r1));
-        // V = U - u_b on Gamma ; F = G^-1 V / (beta dt^2)   (eqs. Vt, L-determination_ND)
-        std::vector<double> g3(3 * c->ng), F(nd);
+        c->green_sweeps = c->green_inner = 0;
+        CHK(green_solve(c, c->b, c->w, std::sqrt(bn), c->opt.tol, false, &r1));
+        // V = U - u_b on Gamma ; F = G^-1 V / (beta dt^2)   (eqs. Vt, L-determination_ND), on
+        // the device: Fdev holds V, then F (d per point), gbuf the force with 3 components
         LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));
-        HIPCHK(c, hipMemcpyAsync(g3.data(), c->gbuf, g3.size() * sizeof(double), hipMemcpyDeviceToHost, s));
-        HIPCHK(c, hipStreamSynchronize(s));
-        for (long pnt = 0; pnt < c->ng; pnt++)
-            for (int j = 0; j < d; j++) F[d * pnt + j] = (per_point ? U3[3 * pnt + j] : U3[j]) - g3[3 * pnt + j];
-        lu_solve(c->LU, nd, c->piv, F.data());
-        double fn = 0;
-        std::vector<double> F3(3 * c->ng, 0.0);
-        for (long pnt = 0; pnt < c->ng; pnt++)
-            for (int j = 0; j < d; j++) {
-                const double f = F[d * pnt + j] / c->sp.bdt2;
-                F[d * pnt + j] = f;
-                F3[3 * pnt + j] = f;
-                fn += f * f;
-            }
+        LCHK(c, launch_green_rhs(c->Fdev, c->gbuf, c->Ubuf, per_point, c->ng, d, s));
+        LCHK(c, lu_solve_device(c->Gdev, nd, c->pivdev, c->Fdev, s));
+        LCHK(c, launch_green_force(c->gbuf, c->Fdev, 1.0 / c->sp.bdt2, c->ng, d, s));
         // f = F on Gamma (reuse b, no longer needed) ; A u_f = f from the previous u_f
         LCHK(c, launch_fill<double>(c->b, 0.0, n, s));
-        HIPCHK(c, hipMemcpyAsync(c->gbuf, F3.data(), F3.size() * sizeof(double), hipMemcpyHostToDevice, s));
         LCHK(c, launch_set_gamma(c->b, c->gidx, c->ng, c->gbuf, 1, 3, c->N, s));
-        CHK(pcg<double>(c, c->b, c->uf, c->r, c->p, c->q, false, false, std::sqrt(fn), c->opt.tol,
-                        c->opt.max_iter, -1, false, &r2));
+        double fn;
+        CHK(norm2<double>(c, c->b, &fn));
+        CHK(green_solve(c, c->b, c->uf, std::sqrt(fn), c->opt.tol, false, &r2));
         // u_n = u_b + beta dt^2 u_f   (eq. Sol_Real_ND)
         LCHK(c, launch_axpby<double>(c->w, c->w, c->uf, c->sp.bdt2, n, s));
         local.iters[0] = r1.iters;
         local.iters[1] = r2.iters;
-        local.relres = std::sqrt(r1.rr) / std::sqrt(bn);
+        local.sweeps = c->green_sweeps;
+        local.inner_iters = c->green_inner;
+        local.relres = c->opt.precision == NM_PREC_MIXED ? 0.0 : std::sqrt(r1.rr) / std::sqrt(bn);
         local.relres0 = std::sqrt(r1.rr0) / std::sqrt(bn);
-        c->F_last = F;
+        c->F_on_device = true;
     } else {
         if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
         if (c->ng > 0 && c->d32_is_x)
@@ -1502,6 +1516,22 @@ int nm_ws_train_residual(nm_ctx* c, const void* feat_dev, const void* rp_dev, do
 }
 
 void* nm_get_stream(nm_ctx* c) { return c ? (void*)c->stream : nullptr; }
+
+int nm_green_solve(nm_ctx* c, const double* V, double* X)
+{
+    if (!c) return NM_EINVAL;
+    if (!c->Gdev || !V || !X) return fail(c, NM_EINVAL, "no Green matrix in this context, or null vectors");
+    const long nd = (long)c->dim * c->ng;
+    double* buf = nullptr;
+    CHK(dalloc(c, &buf, nd));
+    HIPCHK(c, hipMemcpyAsync(buf, V, nd * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    LCHK(c, lu_solve_device(c->Gdev, (int)nd, c->pivdev, buf, c->stream));
+    HIPCHK(c, hipMemcpyAsync(X, buf, nd * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)buf));
+    HIPCHK(c, hipFree(buf));
+    return NM_OK;
+}
 
 int nm_green_matrix(const nm_ctx* c, double* G)
 {

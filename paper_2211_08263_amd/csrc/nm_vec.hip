@@ -551,6 +551,7 @@ template int launch_axpby<double>(double*, const double*, const double*, double,
 template int launch_axpby<float>(float*, const float*, const float*, double, long, hipStream_t);
 template int launch_fill<double>(double*, double, long, hipStream_t);
 template int launch_fill<float>(float*, float, long, hipStream_t);
+template int launch_fill<int>(int*, int, long, hipStream_t);
 template int launch_copy<double>(double*, const double*, long, hipStream_t);
 template int launch_copy<float>(float*, const float*, long, hipStream_t);
 template int launch_dot<double>(const double*, const double*, long, double*, hipStream_t);

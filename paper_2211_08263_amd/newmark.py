@@ -32,7 +32,8 @@ ROUTE_AUTO, ROUTE_GREEN, ROUTE_PROJECTED = 0, 1, 2
 WS_COLD, WS_PREV, WS_TAYLOR, WS_LEARNED = 0, 1, 2, 3
 
 EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_precond_apply", "nm_pcg_solve",
-            "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_get_stream", "nm_profile_passes",
+            "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_green_solve",
+            "nm_get_stream", "nm_profile_passes",
             "nm_net_create", "nm_net_destroy", "nm_net_num_params", "nm_net_get_params", "nm_net_set_params",
             "nm_net_forward", "nm_net_train_step", "nm_net_gradients", "nm_conv3d_bf16", "nm_conv3d_bf16_noalloc",
             "nm_ws_attach",
@@ -56,7 +57,8 @@ class _Problem(C.Structure):
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("route", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("warm_start", C.c_int),
-                ("green_tol", C.c_double), ("compute_reaction", C.c_int), ("true_residual", C.c_int)]
+                ("green_tol", C.c_double), ("compute_reaction", C.c_int), ("true_residual", C.c_int),
+                ("green_in", C.c_void_p)]
 
 
 class StepStats(C.Structure):
@@ -107,6 +109,7 @@ def load_library():
     L.nm_set_state.argtypes = [vp, vp, vp, vp, C.c_int64]
     L.nm_state_device_ptrs.argtypes = [vp, C.POINTER(vp), C.POINTER(vp), C.POINTER(vp)]
     L.nm_green_matrix.argtypes = [vp, vp]
+    L.nm_green_solve.argtypes = [vp, vp, vp]
     L.nm_profile_passes.argtypes = [vp, i, vp, vp, i, i, C.POINTER(C.c_double)]
     L.nm_net_create.argtypes = [C.c_ulonglong, C.POINTER(vp)]
     L.nm_net_destroy.argtypes = [vp]
@@ -152,6 +155,7 @@ class Options:
     green_tol: float = 0.0
     compute_reaction: int = 0
     true_residual: int = 0
+    green_in: Optional[np.ndarray] = None  # stored Green matrix to reuse (GREEN route)
 
 
 class Context:
@@ -217,8 +221,9 @@ def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voi
                   None if u0a is None else u0a.ctypes.data, None if v0a is None else v0a.ctypes.data,
                   float(dt), float(beta), float(gamma_nm))
     o = options or Options()
+    gin = None if o.green_in is None else _c64(o.green_in).reshape(-1)
     op = _Options(o.precision, o.route, o.tol, o.max_iter, o.inner_tol, o.max_sweeps, o.warm_start, o.green_tol,
-                  o.compute_reaction, o.true_residual)
+                  o.compute_reaction, o.true_residual, None if gin is None else gin.ctypes.data)
     out = C.c_void_p()
     code = lib.nm_newmark_init(C.byref(pb), C.byref(op), stream, C.byref(out))
     ctx = Context(out.value, (ph, Cv, rh, g), int(dim), tuple(nn), int(g.size))
@@ -334,6 +339,14 @@ def green_matrix(ctx: Context) -> np.ndarray:
     G = np.empty((nd, nd))
     ctx.check(load_library().nm_green_matrix(ctx.handle, G.ctypes.data))
     return G
+
+
+def green_solve(ctx: Context, V) -> np.ndarray:
+    """G^-1 V with the context's device LU factors (GREEN route)."""
+    Va = _c64(V).reshape(-1)
+    X = np.empty_like(Va)
+    ctx.check(load_library().nm_green_solve(ctx.handle, Va.ctypes.data, X.ctypes.data))
+    return X
 
 
 OPERATOR_PASSES = ("x_fwd", "y_deriv", "z_strain", "x_stress", "y_div", "z_div", "x_inv_inertia")
