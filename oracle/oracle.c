@@ -129,7 +129,15 @@ typedef struct {
     const double *C21;     /* per phase: upper triangle of the Voigt 6x6 */
     const double *rho;     /* per phase */
     double dt, beta, gamma_nm;
+    const double *damp;    /* per phase viscous coefficient c (force -c v), or NULL for none */
 } or_prob;
+
+/* Density seen by the implicit operator: rho + gamma dt c (the viscous term of
+ * M a + C v + K u = f folded in by the Newmark update v_n = v~ + gamma dt a_n). */
+static double rho_op(const or_prob *p, int g)
+{
+    return p->rho[g] + (p->damp ? p->gamma_nm * p->dt * p->damp[g] : 0.0);
+}
 
 /* Voigt index of the symmetric pair (i, j): 11,22,33,23,13,12. */
 static int voigt_index(int i, int j)
@@ -258,7 +266,7 @@ void or_apply(const or_prob *p, const double *u, double *Au)
     or_div_stress(p, u, Au);
     for (int j = 0; j < d; j++)
         for (long v = 0; v < N; v++)
-            Au[j * N + v] = -c * Au[j * N + v] + p->rho[p->phase[v]] * u[j * N + v];
+            Au[j * N + v] = -c * Au[j * N + v] + rho_op(p, p->phase[v]) * u[j * N + v];
 }
 
 /* ------------------------------------------------------------------------- */
@@ -322,7 +330,7 @@ void or_reference_medium(const or_prob *p, double Cbar[81], double *rhobar)
         const double *cg = &C[g][0][0][0][0];
         for (int t = 0; t < 81; t++)
             Cbar[t] += w * cg[t];
-        *rhobar += w * p->rho[g];
+        *rhobar += w * rho_op(p, g);
     }
     free(count);
     free(C);
@@ -666,11 +674,13 @@ int or_newmark(const or_prob *p, const int64_t *gidx, int n_gamma, const or_opts
     for (int pt = 0; pt < n_gamma; pt++)
         for (int j = 0; j < d; j++)
             fixed[j * N + gidx[pt]] = 1;
-    /* initial acceleration: a0 = div(C : grad^s u0) / rho */
+    /* initial acceleration: a0 = (div(C : grad^s u0) - c v0) / rho */
     or_div_stress(p, u, a);
     for (int j = 0; j < d; j++)
-        for (long x = 0; x < N; x++)
-            a[j * N + x] /= p->rho[p->phase[x]];
+        for (long x = 0; x < N; x++) {
+            int g = p->phase[x];
+            a[j * N + x] = (a[j * N + x] - (p->damp ? p->damp[g] * v[j * N + x] : 0.0)) / p->rho[g];
+        }
     if (o->route == OR_ROUTE_GREEN && n_gamma > 0) {
         G = malloc(sizeof(double) * (long)nd * nd);
         piv = malloc(sizeof(int) * nd);
@@ -686,12 +696,16 @@ int or_newmark(const or_prob *p, const int64_t *gidx, int n_gamma, const or_opts
     }
     for (int s = 0; s < n_steps; s++) {
         const double *Us = U + (long)s * (per_point ? nd : d);
-        /* predictor and right-hand side, eq. (Fourier_ND_b) */
+        /* predictor and right-hand side, eq. (Fourier_ND_b); with viscous damping
+         * (rho + gamma dt c) u~ - beta dt^2 c v~, v~ = v + (1 - gamma) dt a */
         for (int j = 0; j < d; j++)
             for (long x = 0; x < N; x++) {
                 long i = j * N + x;
+                int g = p->phase[x];
                 ut[i] = u[i] + dt * v[i] + dt * dt * (0.5 - p->beta) * a[i];
-                b[i] = p->rho[p->phase[x]] * ut[i];
+                b[i] = rho_op(p, g) * ut[i];
+                if (p->damp)
+                    b[i] -= c * p->damp[g] * (v[i] + (1.0 - gam) * dt * a[i]);
             }
         int it1 = -1, it2 = -1, failed = 0;
         int rp1 = o->replay ? o->replay[2 * s] : -1, rp2 = o->replay ? o->replay[2 * s + 1] : -1;

@@ -22,7 +22,7 @@ ROUTE_PROJECTED, ROUTE_GREEN, ROUTE_DENSE = 0, 1, 2
 class _Prob(C.Structure):
     _fields_ = [("d", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("n_phases", C.c_int),
                 ("phase", C.c_void_p), ("C21", C.c_void_p), ("rho", C.c_void_p),
-                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double)]
+                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double), ("damp", C.c_void_p)]
 
 
 class _Opts(C.Structure):
@@ -80,7 +80,7 @@ class OracleProblem:
 
     def __init__(self, dim: int, n: Sequence[int], L: Sequence[float], phase_id: np.ndarray,
                  C21: np.ndarray, rho: np.ndarray, dt: float, beta: float = 0.25,
-                 gamma_nm: float = 0.5):
+                 gamma_nm: float = 0.5, damping=None):
         self.dim = int(dim)
         nn = [int(x) for x in n] + [1] * (3 - len(n))
         self.n = tuple(nn)
@@ -91,13 +91,15 @@ class OracleProblem:
         self.rho = _f64(rho).reshape(-1)
         self.dt, self.beta, self.gamma_nm = float(dt), float(beta), float(gamma_nm)
         LL = [float(x) for x in L] + [1.0] * (3 - len(L))
+        self.damp = None if damping is None else _f64(damping).reshape(-1)
         self.s = _Prob(self.dim, (C.c_int * 3)(*nn), (C.c_double * 3)(*LL), self.C21.shape[0],
                        self.phase.ctypes.data, self.C21.ctypes.data, self.rho.ctypes.data,
-                       self.dt, self.beta, self.gamma_nm)
+                       self.dt, self.beta, self.gamma_nm, None if self.damp is None else self.damp.ctypes.data)
 
     @classmethod
     def from_problem(cls, pb) -> "OracleProblem":
-        return cls(pb.dim, pb.n, pb.L, pb.phase_id, pb.C21, pb.rho, pb.dt, pb.beta, pb.gamma_nm)
+        return cls(pb.dim, pb.n, pb.L, pb.phase_id, pb.C21, pb.rho, pb.dt, pb.beta, pb.gamma_nm,
+                   getattr(pb, "damping", None))
 
     @property
     def field_shape(self):
