@@ -71,6 +71,14 @@ typedef struct nm_problem {
     double dt;                /* time increment */
     double beta;              /* Newmark beta (0.25) */
     double gamma_nm;          /* Newmark gamma (0.5) */
+    const double* damping;    /* host, n_phases viscous coefficients c >= 0 per unit volume, or NULL:
+                                 M a + C v + K u = f with C = diag(c(phase)) (section 5's viscous
+                                 buffer against the second wave of periodic boxes), integrated by
+                                 the same Newmark rule: the operator's density becomes
+                                 rho + gamma dt c and the right-hand side
+                                 (rho + gamma dt c) u~ - beta dt^2 c (v + (1 - gamma) dt a).
+                                 Implicit scheme only (NM_EUNSUPPORTED with beta == 0 and any
+                                 c > 0); all zeros is the undamped problem */
 } nm_problem;
 
 typedef struct nm_options {
@@ -91,6 +99,9 @@ typedef struct nm_options {
                                  nm_green_matrix returns it for this problem and dt) to reuse instead of
                                  the unit-force solves (section 3.2: the preprocessing of an RVE can be
                                  stored and reused), or NULL; host, copied */
+    void (*green_progress)(int64_t done, int64_t total, void* user); /* GREEN route: called after each
+                                 unit-force solve of nm_newmark_init (may be NULL) */
+    void* green_progress_user;
 } nm_options;
 
 typedef struct nm_step_stats {
@@ -114,7 +125,8 @@ typedef struct nm_ctx nm_ctx;
  * tables, the Gamma route (GREEN: d*n_gamma unit-force solves of eq.
  * (solve_green) in the context's precision, or a stored G from options->green_in,
  * the matrix G of eq. (G) on the device and its LU factors with partial pivoting, also
- * on the device) and the initial acceleration a0 = div(C : grad^s u0) / rho.  hip_stream
+ * on the device) and the initial acceleration a0 = (div(C : grad^s u0) - c v0) / rho
+ * (c = 0 without damping).  hip_stream
  * may be NULL (a stream is created).  On success *out owns all resources. */
 int nm_newmark_init(const nm_problem* pb, const nm_options* op, void* hip_stream, nm_ctx** out);
 

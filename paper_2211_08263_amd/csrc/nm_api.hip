@@ -49,8 +49,10 @@ struct nm_ctx {
     int64_t* gidx = nullptr;
     double* C64 = nullptr;
     float* C32 = nullptr;
-    double* rho64 = nullptr;
+    double* rho64 = nullptr;   // operator density rho + gamma dt c (rho without damping)
     float* rho32 = nullptr;
+    double* rhot64 = nullptr;  // true density (aliases rho64 without damping)
+    double* damp64 = nullptr;  // viscous coefficient c per phase, or null
     double2* tw64 = nullptr;
     float2* tw32 = nullptr;
     // scalars and reductions
@@ -560,20 +562,25 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
 
 // Mixed precision without a Gamma projection (the Green route's solves): FP64 residual
 // r = rhs - A x, FP32 PCG correction, x += d, until ||r|| <= tol bref.
-int solve_mixed_plain(nm_ctx* c, const double* rhs, double* x, double bref, double tol, int* sweeps_out,
-                      int* inner_out)
+// rr_out / rr0_out (or null): the last and the first FP64 residual, squared.
+int solve_mixed_plain(nm_ctx* c, const double* rhs, double* x, double bref, double tol, bool x_zero, int* sweeps_out,
+                      int* inner_out, double* rr_out = nullptr, double* rr0_out = nullptr)
 {
     hipStream_t s = c->stream;
     const long n = 3 * c->N;
     if (bref <= 0) bref = 1.0;
     int sweeps = 0, inner = 0;
     for (;;) {
-        CHK(apply_A<double>(c, x, c->q, nullptr));
+        // r = rhs - A x (the first residual of a zero start is rhs itself)
+        if (sweeps == 0 && x_zero) LCHK(c, launch_fill<double>(c->q, 0.0, n, s));
+        else CHK(apply_A<double>(c, x, c->q, nullptr));
         LCHK(c, launch_residual<double>(rhs, c->q, c->r, nullptr, c->N, 3, c->part_a, s, c->r32));
         LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
         CHK(read_scalars(c));
         const double rr = c->hscal[S_RR];
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual in refinement sweep %d", sweeps);
+        if (sweeps == 0 && rr0_out) *rr0_out = rr;
+        if (rr_out) *rr_out = rr;
         if (std::sqrt(rr) <= tol * bref) break;
         if (sweeps >= c->opt.max_sweeps)
             return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps (rel %.3g)", tol, sweeps,
@@ -599,7 +606,7 @@ int green_solve(nm_ctx* c, const double* rhs, double* x, double bref, double tol
     if (c->opt.precision == NM_PREC_MIXED) {
         *res = PcgResult{};
         res->converged = true;
-        return solve_mixed_plain(c, rhs, x, bref, tol, &c->green_sweeps, &c->green_inner);
+        return solve_mixed_plain(c, rhs, x, bref, tol, x_zero, &c->green_sweeps, &c->green_inner, &res->rr, &res->rr0);
     }
     return pcg<double>(c, rhs, x, c->r, c->p, c->q, false, x_zero, bref, tol, c->opt.max_iter, -1, false, res);
 }
@@ -644,6 +651,7 @@ int build_green(nm_ctx* c, const double* G_in)
                 LCHK(c, launch_green_column(c->Gdev, nd, d * pnt + j, c->gbuf, c->ng, d, s));
                 // unit is a stack buffer that the next copy overwrites
                 HIPCHK(c, hipStreamSynchronize(s));
+                if (c->opt.green_progress) c->opt.green_progress(d * pnt + j + 1, nd, c->opt.green_progress_user);
             }
         std::vector<double> cm((size_t)nd * nd);
         HIPCHK(c, hipMemcpy(cm.data(), c->Gdev, cm.size() * sizeof(double), hipMemcpyDeviceToHost));
@@ -896,12 +904,27 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     c->sp.inv_n2 = 1.0 / c->n2;
     c->sp.inv_n3 = 1.0 / c->n3;
     c->sp.bdt2 = c->beta * c->dt * c->dt;
+    // viscous damping (section 5's buffer): M a + C v + K u = f under the same Newmark rule
+    // gives the operator density rho + gamma dt c; all-zero coefficients are no damping
+    bool damped = false;
+    if (pb->damping) {
+        for (int g = 0; g < c->nph; g++) {
+            if (!(pb->damping[g] >= 0) || !std::isfinite(pb->damping[g]))
+                return fail(c, NM_EINVAL, "damping of phase %d must be finite and >= 0", g);
+            damped = damped || pb->damping[g] > 0;
+        }
+        if (damped && c->explicit_scheme)
+            return fail(c, NM_EUNSUPPORTED, "viscous damping needs the implicit scheme (beta > 0)");
+    }
+    std::vector<double> rho_op(pb->rho, pb->rho + c->nph);
+    if (damped)
+        for (int g = 0; g < c->nph; g++) rho_op[g] = pb->rho[g] + c->gam * c->dt * pb->damping[g];
     c->sp.rhobar = 0;
     for (int k = 0; k < 21; k++) c->sp.Cbar[k] = 0;
     for (int g = 0; g < c->nph; g++) {
         if (!(pb->rho[g] > 0)) return fail(c, NM_EINVAL, "density of phase %d must be positive", g);
         const double wgt = (double)count[g] / (double)c->N;
-        c->sp.rhobar += wgt * pb->rho[g];
+        c->sp.rhobar += wgt * rho_op[g];
         for (int k = 0; k < 21; k++) {
             if (!std::isfinite(pb->C_voigt[21 * g + k])) return fail(c, NM_EINVAL, "non-finite stiffness");
             c->sp.Cbar[k] += wgt * pb->C_voigt[21 * g + k];
@@ -931,15 +954,22 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     {
         std::vector<float> c32(21 * (size_t)c->nph), r32(c->nph);
         for (size_t i = 0; i < c32.size(); i++) c32[i] = (float)pb->C_voigt[i];
-        for (int g = 0; g < c->nph; g++) r32[g] = (float)pb->rho[g];
+        for (int g = 0; g < c->nph; g++) r32[g] = (float)rho_op[g];
         CHK(dalloc(c, &c->C64, 21 * (size_t)c->nph));
         CHK(dalloc(c, &c->C32, 21 * (size_t)c->nph));
         CHK(dalloc(c, &c->rho64, c->nph));
         CHK(dalloc(c, &c->rho32, c->nph));
         HIPCHK(c, hipMemcpy(c->C64, pb->C_voigt, 21 * c->nph * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(c, hipMemcpy(c->C32, c32.data(), c32.size() * sizeof(float), hipMemcpyHostToDevice));
-        HIPCHK(c, hipMemcpy(c->rho64, pb->rho, c->nph * sizeof(double), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(c->rho64, rho_op.data(), c->nph * sizeof(double), hipMemcpyHostToDevice));
         HIPCHK(c, hipMemcpy(c->rho32, r32.data(), r32.size() * sizeof(float), hipMemcpyHostToDevice));
+        c->rhot64 = c->rho64;
+        if (damped) {
+            CHK(dalloc(c, &c->rhot64, c->nph));
+            CHK(dalloc(c, &c->damp64, c->nph));
+            HIPCHK(c, hipMemcpy(c->rhot64, pb->rho, c->nph * sizeof(double), hipMemcpyHostToDevice));
+            HIPCHK(c, hipMemcpy(c->damp64, pb->damping, c->nph * sizeof(double), hipMemcpyHostToDevice));
+        }
     }
     {
         std::vector<double2> t64;
@@ -999,6 +1029,10 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
         // a0 = div(C : grad^s u0) / rho
         CHK(div_stress(c, c->u, c->q, 1.0));
         LCHK(c, launch_div_rho(c->a, c->q, c->phase, c->rho64, c->N, s));
+    } else if (damped && (pb->u0 || pb->v0)) {
+        // a0 = (div(C : grad^s u0) - c v0) / rho
+        if (pb->u0) CHK(div_stress(c, c->u, c->q, 1.0));
+        LCHK(c, launch_accel0_damped(c->a, pb->u0 ? c->q : nullptr, c->v, c->phase, c->rhot64, c->damp64, c->N, 3, s));
     } else if (pb->u0) {
         // a0 = div(C : grad^s u0) / rho
         CHK(apply_A<double>(c, c->u, c->q, nullptr));
@@ -1053,7 +1087,8 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     const bool sfeat_ok = c->pred_ready && c->sfeat_ready;
     c->sfeat_ready = false;
     if (!c->pred_ready)
-        LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+        LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->damp64, c->N, 3, c->dt, c->beta,
+                             c->gam, s));
     c->pred_ready = false;
     c->d32_is_x = false;
     // initial guess
@@ -1116,8 +1151,9 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         local.iters[1] = r2.iters;
         local.sweeps = c->green_sweeps;
         local.inner_iters = c->green_inner;
-        local.relres = c->opt.precision == NM_PREC_MIXED ? 0.0 : std::sqrt(r1.rr) / std::sqrt(bn);
-        local.relres0 = std::sqrt(r1.rr0) / std::sqrt(bn);
+        // (a zero right-hand side, as at the first step from rest, is solved exactly)
+        local.relres = bn > 0 ? std::sqrt(r1.rr / bn) : 0.0;
+        local.relres0 = bn > 0 ? std::sqrt(r1.rr0 / bn) : 0.0;
         c->F_on_device = true;
     } else {
         if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
@@ -1170,8 +1206,8 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
     // u <- u_n (pointer swap)
     // with the learned start the corrector also leaves the next step's state features
     uint16_t* sf = (c->opt.warm_start == NM_WS_LEARNED && c->net && c->sfeat) ? c->sfeat : nullptr;
-    LCHK(c, launch_corrector_predictor(c->w, c->ut, c->v, c->a, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta,
-                                       c->gam, c->winc, sf, s));
+    LCHK(c, launch_corrector_predictor(c->w, c->ut, c->v, c->a, c->b, c->phase, c->rho64, c->damp64, c->N, 3, c->dt,
+                                       c->beta, c->gam, c->winc, sf, s));
     c->sfeat_ready = sf != nullptr;
     std::swap(c->u, c->w);
     HIPCHK(c, hipStreamSynchronize(s));
@@ -1270,7 +1306,7 @@ int nm_omega2_max(nm_ctx* c, void* x_dev, int iters, double* omega2)
     double lam = 0.0;
     for (int it = 0; it <= iters; it++) {
         // x <- x / |x|_rho
-        LCHK(c, launch_rho_norm2(x, c->phase, c->rho64, c->N, c->part_a, s));
+        LCHK(c, launch_rho_norm2(x, c->phase, c->rhot64, c->N, c->part_a, s));
         LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_SLOT, 6, s));
         CHK(read_scalars(c));
         const double m = c->hscal[6];
@@ -1281,7 +1317,7 @@ int nm_omega2_max(nm_ctx* c, void* x_dev, int iters, double* omega2)
         CHK(dot64(c, x, y, &lam));
         if (it == iters) break;
         // x <- rho^-1 K x
-        LCHK(c, launch_div_rho(x, y, c->phase, c->rho64, c->N, s));
+        LCHK(c, launch_div_rho(x, y, c->phase, c->rhot64, c->N, s));
     }
     HIPCHK(c, hipStreamSynchronize(s));
     *omega2 = lam;
@@ -1420,7 +1456,8 @@ int nm_ws_features(nm_ctx* c, void* feat_dev)
     if (!c || !c->feat) return fail(c, NM_EINVAL, "call nm_ws_attach first");
     hipStream_t s = c->stream;
     // predictor of the next step (the step recomputes the same values)
-    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->damp64, c->N, 3, c->dt, c->beta,
+                             c->gam, s));
     nm::WarmArgs a = warm_args(c);
     if (feat_dev) a.feat = (uint16_t*)feat_dev;
     LCHK(c, nm::warm_features(a, s));
@@ -1432,7 +1469,8 @@ int nm_ws_predict(nm_ctx* c, void* x0_dev)
 {
     if (!c || !c->net || !x0_dev) return fail(c, NM_EINVAL, "attach a network and pass x0");
     hipStream_t s = c->stream;
-    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->damp64, c->N, 3, c->dt, c->beta,
+                             c->gam, s));
     int e = nm::warm_predict(c->net, warm_args(c), (double*)x0_dev, s);
     if (e) return fail(c, e == -1 ? NM_EUNSUPPORTED : NM_EHIP, "warm-start network failed");
     HIPCHK(c, hipStreamSynchronize(s));
@@ -1458,7 +1496,8 @@ int nm_ws_residual_sample(nm_ctx* c, const double* U_next, int per_point, void* 
     std::vector<double> U3;
     CHK(upload_U(c, U_next, per_point, U3));
     // predictor, b = rho u~, features and scale of the coming step
-    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->N, 3, c->dt, c->beta, s));
+    LCHK(c, launch_predictor(c->u, c->v, c->a, c->ut, c->b, c->phase, c->rho64, c->damp64, c->N, 3, c->dt, c->beta,
+                             c->gam, s));
     nm::WarmArgs a = warm_args(c);
     a.feat = (uint16_t*)feat_dev;
     LCHK(c, nm::warm_features(a, s));

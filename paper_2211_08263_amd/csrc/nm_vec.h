@@ -55,21 +55,28 @@ int launch_set_gamma_f32(float* x, const int64_t* gidx, long ng, const double* U
 // out[dim*p + j] = x[j*N + gidx[p]]
 int launch_gather_gamma(double* out, const double* x, const int64_t* gidx, long ng, int dim, long N, hipStream_t s);
 
-// Newmark predictor: ut = u + dt v + dt^2 (1/2 - beta) a ; b = rho(phase) ut
+// Newmark predictor: ut = u + dt v + dt^2 (1/2 - beta) a ; b = rho(phase) ut, and with a
+// viscous coefficient per phase (damp, or null) b -= beta dt^2 damp(phase) (v + (1 - gamma) dt a).
+// rho is the operator density (rho + gamma dt damp with damping).
 int launch_predictor(const double* u, const double* v, const double* a, double* ut, double* b,
-                     const uint16_t* phase, const double* rho, long N, int ncomp, double dt, double beta,
-                     hipStream_t s);
+                     const uint16_t* phase, const double* rho, const double* damp, long N, int ncomp, double dt,
+                     double beta, double gam, hipStream_t s);
 // Newmark corrector (an = (un - ut)/(beta dt^2); v += dt((1-g) a + g an); a = an) fused
-// with the next predictor (ut = un + dt v + dt^2 (1/2 - beta) a) and b = rho ut.
+// with the next predictor (ut = un + dt v + dt^2 (1/2 - beta) a) and b = rho ut (damping as in
+// launch_predictor, with the new v and a).
 // inc (or null): corrector_blocks(N) per-block sums of |ut_new - un|^2; feat (or null):
 // unscaled BF16 state features [N][16] of the new state (u, dt v, dt^2 (1/2 - beta) a).
 int corrector_blocks(long N);
 int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
-                               const double* rho, long N, int ncomp, double dt, double beta, double gam, double* inc,
-                               uint16_t* feat, hipStream_t s);
+                               const double* rho, const double* damp, long N, int ncomp, double dt, double beta,
+                               double gam, double* inc, uint16_t* feat, hipStream_t s);
 // Initial acceleration from q = A u0: a0 = (rho u0 - q) / (beta dt^2 rho) = div(C : grad^s u0) / rho
 int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* phase, const double* rho, long N,
                   int ncomp, double bdt2, hipStream_t s);
+// Initial acceleration with viscous damping: a0 = (q - damp(phase) v0) / rho(phase), q = div(C :
+// grad^s u0) (null for u0 = 0), rho the true density.
+int launch_accel0_damped(double* a, const double* q, const double* v, const uint16_t* phase, const double* rho,
+                         const double* damp, long N, int ncomp, hipStream_t s);
 // Explicit central-difference scheme, Gamma voxels after the velocity pass: with vb = v there,
 // f = 2 rho / dt (Udot - vb), v = Udot, a += f / rho, F[dim*p + j] = f (eq.
 // Explicit_linear_momentum_arranged_3D and the force that prescribes the velocity).

@@ -353,21 +353,25 @@ int launch_gather_gamma(double* out, const double* x, const int64_t* gidx, long 
 __global__ __launch_bounds__(kBlock) void k_predictor(const double* __restrict__ u, const double* __restrict__ v,
                                                       const double* __restrict__ a, double* __restrict__ ut,
                                                       double* __restrict__ b, const uint16_t* __restrict__ phase,
-                                                      const double* __restrict__ rho, long N, long n, double dt,
-                                                      double c2)
+                                                      const double* __restrict__ rho, const double* __restrict__ damp,
+                                                      long N, long n, double dt, double c2, double bdt2, double gdt1)
 {
     for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
         const double w = u[i] + dt * v[i] + c2 * a[i];
+        const int g = phase[i % N];
         ut[i] = w;
-        b[i] = rho[phase[i % N]] * w;
+        double bi = rho[g] * w;
+        if (damp) bi -= bdt2 * damp[g] * (v[i] + gdt1 * a[i]);
+        b[i] = bi;
     }
 }
 int launch_predictor(const double* u, const double* v, const double* a, double* ut, double* b, const uint16_t* phase,
-                     const double* rho, long N, int ncomp, double dt, double beta, hipStream_t s)
+                     const double* rho, const double* damp, long N, int ncomp, double dt, double beta, double gam,
+                     hipStream_t s)
 {
     const long n = N * ncomp;
-    hipLaunchKernelGGL(k_predictor, dim3(vec_blocks(n)), dim3(kBlock), 0, s, u, v, a, ut, b, phase, rho, N, n, dt,
-                       dt * dt * (0.5 - beta));
+    hipLaunchKernelGGL(k_predictor, dim3(vec_blocks(n)), dim3(kBlock), 0, s, u, v, a, ut, b, phase, rho, damp, N, n,
+                       dt, dt * dt * (0.5 - beta), beta * dt * dt, (1.0 - gam) * dt);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -382,7 +386,8 @@ __device__ __forceinline__ uint16_t bf16_rne(float f)
 
 // Corrector of this step fused with the predictor of the next one:
 // a_n = (u_n - u~)/(beta dt^2), v_n = v + dt((1 - gamma) a + gamma a_n), then
-// u~' = u_n + dt v_n + dt^2 (1/2 - beta) a_n and b' = rho u~' (ut and b overwritten).
+// u~' = u_n + dt v_n + dt^2 (1/2 - beta) a_n and b' = rho u~' (ut and b overwritten; with
+// damping b' = rho u~' - beta dt^2 c (v_n + (1 - gamma) dt a_n), rho the operator density).
 // inc (or null): per-block sums of |u~' - u_n|^2 (the learned start's scale).
 // feat (or null): the learned start's state features of the new state, unscaled, BF16
 // [N][16]: (u_n, dt v_n, dt^2 (1/2 - beta) a_n) per component, channels 9..15 zero.
@@ -391,13 +396,17 @@ __global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __
                                                                 double* __restrict__ v, double* __restrict__ a,
                                                                 double* __restrict__ b,
                                                                 const uint16_t* __restrict__ phase,
-                                                                const double* __restrict__ rho, long N,
+                                                                const double* __restrict__ rho,
+                                                                const double* __restrict__ damp, long N,
                                                                 double dt, double inv_bdt2, double gam, double c2,
+                                                                double bdt2, double gdt1,
                                                                 double* __restrict__ inc, uint16_t* __restrict__ feat)
 {
     double acc = 0.0;
     for (long p = (long)blockIdx.x * blockDim.x + threadIdx.x; p < N; p += (long)gridDim.x * blockDim.x) {
-        const double rp = rho[phase[p]];
+        const int g = phase[p];
+        const double rp = rho[g];
+        const double cb = damp ? bdt2 * damp[g] : 0.0;
         uint16_t f[16];
 #pragma unroll
         for (int k = 0; k < 16; k++) f[k] = 0;
@@ -411,7 +420,9 @@ __global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __
             a[i] = an;
             const double w = u + dt * vn + c2 * an;
             ut[i] = w;
-            b[i] = rp * w;
+            double bi = rp * w;
+            if (damp) bi -= cb * (vn + gdt1 * an);
+            b[i] = bi;
             acc += (w - u) * (w - u);
             f[c] = bf16_rne((float)u);
             f[3 + c] = bf16_rne((float)(dt * vn));
@@ -442,12 +453,13 @@ __global__ __launch_bounds__(kBlock) void k_corrector_predictor(const double* __
 }
 int corrector_blocks(long N) { return vec_blocks(N); }
 int launch_corrector_predictor(const double* un, double* ut, double* v, double* a, double* b, const uint16_t* phase,
-                               const double* rho, long N, int ncomp, double dt, double beta, double gam,
-                               double* inc, uint16_t* feat, hipStream_t s)
+                               const double* rho, const double* damp, long N, int ncomp, double dt, double beta,
+                               double gam, double* inc, uint16_t* feat, hipStream_t s)
 {
     if (ncomp != 3) return -1;
     hipLaunchKernelGGL(k_corrector_predictor, dim3(corrector_blocks(N)), dim3(kBlock), 0, s, un, ut, v, a, b, phase,
-                       rho, N, dt, 1.0 / (beta * dt * dt), gam, dt * dt * (0.5 - beta), inc, feat);
+                       rho, damp, N, dt, 1.0 / (beta * dt * dt), gam, dt * dt * (0.5 - beta), beta * dt * dt,
+                       (1.0 - gam) * dt, inc, feat);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -466,6 +478,23 @@ int launch_accel0(double* a, const double* u0, const double* q, const uint16_t* 
 {
     const long n = N * ncomp;
     hipLaunchKernelGGL(k_accel0, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, u0, q, phase, rho, N, n, bdt2);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(kBlock) void k_accel0_damped(double* a, const double* q, const double* v,
+                                                          const uint16_t* phase, const double* rho,
+                                                          const double* damp, long N, long n)
+{
+    for (long i = (long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long)gridDim.x * blockDim.x) {
+        const int g = phase[i % N];
+        a[i] = ((q ? q[i] : 0.0) - damp[g] * v[i]) / rho[g];
+    }
+}
+int launch_accel0_damped(double* a, const double* q, const double* v, const uint16_t* phase, const double* rho,
+                         const double* damp, long N, int ncomp, hipStream_t s)
+{
+    const long n = N * ncomp;
+    hipLaunchKernelGGL(k_accel0_damped, dim3(vec_blocks(n)), dim3(kBlock), 0, s, a, q, v, phase, rho, damp, N, n);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 

@@ -51,14 +51,17 @@ class _Problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("n_phases", C.c_int),
                 ("phase_id", C.c_void_p), ("C_voigt", C.c_void_p), ("rho", C.c_void_p),
                 ("gamma_idx", C.c_void_p), ("n_gamma", C.c_int64), ("u0", C.c_void_p), ("v0", C.c_void_p),
-                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double)]
+                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double), ("damping", C.c_void_p)]
 
 
 class _Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("route", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("warm_start", C.c_int),
                 ("green_tol", C.c_double), ("compute_reaction", C.c_int), ("true_residual", C.c_int),
-                ("green_in", C.c_void_p)]
+                ("green_in", C.c_void_p), ("green_progress", C.c_void_p), ("green_progress_user", C.c_void_p)]
+
+
+GREEN_PROGRESS = C.CFUNCTYPE(None, C.c_int64, C.c_int64, C.c_void_p)
 
 
 class StepStats(C.Structure):
@@ -156,6 +159,7 @@ class Options:
     compute_reaction: int = 0
     true_residual: int = 0
     green_in: Optional[np.ndarray] = None  # stored Green matrix to reuse (GREEN route)
+    green_progress: object = None  # callable(done, total) after each unit-force solve (GREEN route)
 
 
 class Context:
@@ -206,7 +210,8 @@ def _c64(a):
 
 def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voigt, rho, gamma_idx, dt: float,
                  beta: float = 0.25, gamma_nm: float = 0.5, u0=None, v0=None, options: Optional[Options] = None,
-                 stream=None) -> Context:
+                 stream=None, damping=None) -> Context:
+    """damping: per-phase viscous coefficients c >= 0 (force -c v), or None."""
     lib = load_library()
     nn = [int(x) for x in n] + [1] * (3 - len(n))
     LL = [float(x) for x in L] + [1.0] * (3 - len(L))
@@ -216,17 +221,25 @@ def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voi
     g = np.ascontiguousarray(gamma_idx, dtype=np.int64).reshape(-1)
     u0a = None if u0 is None else _c64(u0).reshape(-1)
     v0a = None if v0 is None else _c64(v0).reshape(-1)
+    dm = None if damping is None else _c64(damping).reshape(-1)
+    if dm is not None and dm.size != rh.size:
+        raise ValueError("damping needs one coefficient per phase")
     pb = _Problem(int(dim), (C.c_int * 3)(*nn), (C.c_double * 3)(*LL), rh.size, ph.ctypes.data, Cv.ctypes.data,
                   rh.ctypes.data, g.ctypes.data if g.size else None, g.size,
                   None if u0a is None else u0a.ctypes.data, None if v0a is None else v0a.ctypes.data,
-                  float(dt), float(beta), float(gamma_nm))
+                  float(dt), float(beta), float(gamma_nm), None if dm is None else dm.ctypes.data)
     o = options or Options()
     gin = None if o.green_in is None else _c64(o.green_in).reshape(-1)
+    cb = None
+    if o.green_progress is not None:
+        user_cb = o.green_progress
+        cb = GREEN_PROGRESS(lambda done, total, _u: user_cb(int(done), int(total)))
     op = _Options(o.precision, o.route, o.tol, o.max_iter, o.inner_tol, o.max_sweeps, o.warm_start, o.green_tol,
-                  o.compute_reaction, o.true_residual, None if gin is None else gin.ctypes.data)
+                  o.compute_reaction, o.true_residual, None if gin is None else gin.ctypes.data,
+                  None if cb is None else C.cast(cb, C.c_void_p).value, None)
     out = C.c_void_p()
     code = lib.nm_newmark_init(C.byref(pb), C.byref(op), stream, C.byref(out))
-    ctx = Context(out.value, (ph, Cv, rh, g), int(dim), tuple(nn), int(g.size))
+    ctx = Context(out.value, (ph, Cv, rh, g, dm), int(dim), tuple(nn), int(g.size))
     if code != NM_OK:
         msg = ctx.last_error() if out.value else ""
         ctx.close()
@@ -237,7 +250,7 @@ def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voi
 def newmark_init_problem(pb, options: Optional[Options] = None, u0=None, v0=None, stream=None) -> Context:
     """newmark_init from a workloads.Problem."""
     return newmark_init(pb.dim, pb.n, pb.L, pb.phase_id, pb.C21, pb.rho, pb.gamma_idx, pb.dt, pb.beta, pb.gamma_nm,
-                        u0=u0, v0=v0, options=options, stream=stream)
+                        u0=u0, v0=v0, options=options, stream=stream, damping=getattr(pb, "damping", None))
 
 
 def newmark_step(ctx: Context, U, per_point: bool = False) -> dict:

@@ -320,6 +320,7 @@ class Problem:
     pulse_dir: Tuple[float, float, float] = (1.0, 0.0, 0.0)
     n_steps: int = 0
     tol: float = 1e-8
+    damping: Optional[np.ndarray] = None  # (n_phases,) viscous coefficients (force -c v), or None
 
     @property
     def n_vox(self) -> int:

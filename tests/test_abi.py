@@ -74,6 +74,9 @@ def _bad_init(**change):
     ("non-positive dt", "EINVAL"),
     ("non-positive tol", "EINVAL"),
     ("unknown warm start", "EINVAL"),
+    ("negative damping", "EINVAL"),
+    ("non-finite damping", "EINVAL"),
+    ("damping in the explicit scheme", "EUNSUPPORTED"),
 ])
 def test_init_rejects_bad_arguments(case, code):
     import numpy as np
@@ -94,5 +97,8 @@ def test_init_rejects_bad_arguments(case, code):
         "non-positive dt": dict(dt=0.0),
         "non-positive tol": dict(options=nmb.Options(tol=0.0)),
         "unknown warm start": dict(options=nmb.Options(warm_start=9)),
+        "negative damping": dict(damping=np.array([0.0, -1.0, 0.0, 0.0])),
+        "non-finite damping": dict(damping=np.array([0.0, np.nan, 0.0, 0.0])),
+        "damping in the explicit scheme": dict(damping=np.array([0.0, 1.0, 0.0, 0.0]), beta=0.0),
     }[case]
     assert _bad_init(**change) == getattr(nmb, "NM_" + code)

@@ -98,3 +98,6 @@ def test_mixed_precision_green_route():
     assert e_or <= 1e-5
     assert e_rt <= 1e-5
     assert all(x["sweeps"] >= 2 for x in st)
+    # the FP64 residual of the u_b solve (zero at the first step, whose right-hand side is zero)
+    assert all(x["relres"] <= 1e-10 and x["relres0"] >= x["relres"] for x in st)
+    assert all(x["relres"] > 0 for x in st[1:])
