@@ -22,7 +22,8 @@ ROUTE_PROJECTED, ROUTE_GREEN, ROUTE_DENSE = 0, 1, 2
 class _Prob(C.Structure):
     _fields_ = [("d", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("n_phases", C.c_int),
                 ("phase", C.c_void_p), ("C21", C.c_void_p), ("rho", C.c_void_p),
-                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double), ("damp", C.c_void_p)]
+                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double), ("damp", C.c_void_p),
+                ("diff_rule", C.c_int)]
 
 
 class _Opts(C.Structure):
@@ -40,6 +41,8 @@ def lib():
         L.or_fftn.argtypes = [vp, i, vp, i]
         L.or_xi.argtypes = [i, i, d]
         L.or_xi.restype = d
+        L.or_xi_rule.argtypes = [i, i, d, i]
+        L.or_xi_rule.restype = d
         for f in ("or_apply", "or_precond", "or_div_stress", "or_stress"):
             getattr(L, f).argtypes = [P, vp, vp]
         L.or_deriv.argtypes = [P, vp, i, vp]
@@ -80,7 +83,7 @@ class OracleProblem:
 
     def __init__(self, dim: int, n: Sequence[int], L: Sequence[float], phase_id: np.ndarray,
                  C21: np.ndarray, rho: np.ndarray, dt: float, beta: float = 0.25,
-                 gamma_nm: float = 0.5, damping=None):
+                 gamma_nm: float = 0.5, damping=None, diff_rule: int = 0):
         self.dim = int(dim)
         nn = [int(x) for x in n] + [1] * (3 - len(n))
         self.n = tuple(nn)
@@ -94,12 +97,14 @@ class OracleProblem:
         self.damp = None if damping is None else _f64(damping).reshape(-1)
         self.s = _Prob(self.dim, (C.c_int * 3)(*nn), (C.c_double * 3)(*LL), self.C21.shape[0],
                        self.phase.ctypes.data, self.C21.ctypes.data, self.rho.ctypes.data,
-                       self.dt, self.beta, self.gamma_nm, None if self.damp is None else self.damp.ctypes.data)
+                       self.dt, self.beta, self.gamma_nm, None if self.damp is None else self.damp.ctypes.data,
+                       int(diff_rule))
+        self.diff_rule = int(diff_rule)
 
     @classmethod
     def from_problem(cls, pb) -> "OracleProblem":
         return cls(pb.dim, pb.n, pb.L, pb.phase_id, pb.C21, pb.rho, pb.dt, pb.beta, pb.gamma_nm,
-                   getattr(pb, "damping", None))
+                   getattr(pb, "damping", None), getattr(pb, "diff_rule", 0))
 
     @property
     def field_shape(self):
@@ -253,6 +258,11 @@ def fftn(a: np.ndarray, sign: int = -1) -> np.ndarray:
 
 def xi(k: int, n: int, L: float) -> float:
     return float(lib().or_xi(int(k), int(n), float(L)))
+
+
+def xi_rule(k: int, n: int, L: float, rule: int) -> float:
+    """Frequency of bin k under a differentiation rule (0 spectral, 1 and 2 centred differences)."""
+    return float(lib().or_xi_rule(int(k), int(n), float(L), int(rule)))
 
 
 def lu_factor(A: np.ndarray):
