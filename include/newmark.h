@@ -52,6 +52,12 @@ enum nm_dtype { NM_FP64 = 0, NM_FP32 = 1 };
 enum nm_precision { NM_PREC_FP64 = 0, NM_PREC_MIXED = 1 };
 enum nm_route { NM_ROUTE_AUTO = 0, NM_ROUTE_GREEN = 1, NM_ROUTE_PROJECTED = 2 };
 enum nm_warm_start { NM_WS_COLD = 0, NM_WS_PREV = 1, NM_WS_TAYLOR = 2, NM_WS_LEARNED = 3 };
+/* Differentiation rules: the symbol of D_k in eq. Fourier_ND_A, the preconditioner of eq. precond
+ * and both time steppers.  SPECTRAL: i xi_k (the paper's; Nyquist bin zero).  CENTRED2: the
+ * centred difference (f(x+h) - f(x-h))/(2h), symbol i sin(xi_k h)/h.  CENTRED4: the fourth-order
+ * centred difference (-f(x+2h) + 8 f(x+h) - 8 f(x-h) + f(x-2h))/(12h), symbol
+ * i (8 sin(xi_k h) - sin(2 xi_k h))/(6h).  h = L_k / n_k. */
+enum nm_diff_rule { NM_DIFF_SPECTRAL = 0, NM_DIFF_CENTRED2 = 1, NM_DIFF_CENTRED4 = 2 };
 
 /* Inputs of the paper's Algorithm 2 (KwData): microstructure, Gamma, initial
  * state, time increment and Newmark constants.  Host arrays are copied by
@@ -79,6 +85,8 @@ typedef struct nm_problem {
                                  (rho + gamma dt c) u~ - beta dt^2 c (v + (1 - gamma) dt a).
                                  Implicit scheme only (NM_EUNSUPPORTED with beta == 0 and any
                                  c > 0); all zeros is the undamped problem */
+    int diff_rule;            /* nm_diff_rule: the derivative's Fourier symbol (section 5 suggests discrete
+                                 finite-difference rules against the noise of large contrast) */
 } nm_problem;
 
 typedef struct nm_options {

@@ -932,6 +932,8 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
     }
     if (!(pb->L[0] > 0) || !(pb->L[1] > 0) || (c->dim == 3 && !(pb->L[2] > 0)))
         return fail(c, NM_EINVAL, "box lengths must be positive");
+    if (pb->diff_rule < NM_DIFF_SPECTRAL || pb->diff_rule > NM_DIFF_CENTRED4)
+        return fail(c, NM_EINVAL, "unknown differentiation rule %d", pb->diff_rule);
 
     // stream
     if (c->stream == nullptr) {
@@ -980,6 +982,24 @@ static int init_impl(nm_ctx* c, const nm_problem* pb, const nm_options* op)
         CHK(dalloc(c, &c->tw32, t32.size()));
         HIPCHK(c, hipMemcpy(c->tw64, t64.data(), t64.size() * sizeof(double2), hipMemcpyHostToDevice));
         HIPCHK(c, hipMemcpy(c->tw32, t32.data(), t32.size() * sizeof(float2), hipMemcpyHostToDevice));
+    }
+    if (pb->diff_rule != NM_DIFF_SPECTRAL) {
+        // the frequency each bin's derivative uses under the finite-difference rule
+        const int na[3] = {c->n1, c->n2, c->n3};
+        const double La[3] = {c->sp.L1, c->sp.L2, c->sp.L3};
+        std::vector<double> mf;
+        for (int ax = 0; ax < 3; ax++) {
+            const double h = La[ax] / na[ax];
+            for (int k = 0; k < na[ax]; k++) {
+                const double th = 2.0 * M_PI * freq_index(k, na[ax]) / na[ax]; // xi h
+                mf.push_back(pb->diff_rule == NM_DIFF_CENTRED2 ? std::sin(th) / h
+                                                               : (8.0 * std::sin(th) - std::sin(2.0 * th)) / (6.0 * h));
+            }
+        }
+        double* mfd = nullptr;
+        CHK(dalloc(c, &mfd, mf.size()));
+        HIPCHK(c, hipMemcpy(mfd, mf.data(), mf.size() * sizeof(double), hipMemcpyHostToDevice));
+        c->sp.mfreq = mfd;
     }
     CHK(dalloc(c, &c->scal, S_COUNT));
     HIPCHK(c, hipMemset(c->scal, 0, S_COUNT * sizeof(double)));

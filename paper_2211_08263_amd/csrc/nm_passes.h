@@ -17,7 +17,12 @@ struct SpecParams {
     double rhobar;    // volume-averaged density
     double Cbar[21];  // volume-averaged Voigt stiffness (upper triangle, row major)
     const double* stop = nullptr; // device flag: when non-zero, kernels given this struct exit at once
+    // Finite-difference differentiation rules: device table of the frequency each bin's
+    // derivative uses in place of the spectral xi (n1 + n2 + n3 entries, axis after axis, indexed
+    // by bin), or null for the spectral derivative.
+    const double* mfreq = nullptr;
 };
+
 
 // Layout of a half-spectrum buffer: element (c, kz, ky, kx) at
 // c * cs + kz * ps + ky * M + kx.  The plane and component strides may carry

@@ -568,6 +568,21 @@ __global__ __launch_bounds__(BLK) void k_ypass(cx_t<T>* __restrict__ data, long 
     for (int m = 0; m < R; m++) col[(long)(t + m * G) * colstride] = v[m];
 }
 
+// Frequency of x bin kx (0 <= kx < n1/2; slot 0 also carries the Nyquist bin, zero under every
+// rule), of y bin ky and of z bin kz, in the same units as k1 kx.
+__device__ __forceinline__ double freq_x(const SpecParams& sp, int kx)
+{
+    return sp.mfreq ? sp.mfreq[kx] : sp.k1 * kx;
+}
+__device__ __forceinline__ double freq_y(const SpecParams& sp, int ky)
+{
+    return sp.mfreq ? sp.mfreq[sp.n1 + ky] : sp.k2 * freq_index(ky, sp.n2);
+}
+__device__ __forceinline__ double freq_z(const SpecParams& sp, int kz)
+{
+    return sp.mfreq ? sp.mfreq[sp.n1 + sp.n2 + kz] : sp.k3 * freq_index(kz, sp.n3);
+}
+
 // Pointwise operators at frequency (xi1, xi2, xi3).
 template <typename T> struct ZOps {
     using V = cx_t<T>;
@@ -629,7 +644,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     }
     ColAddrT<TXC> addr{c, TX};
     const V* twL = twsm;
-    const T xi1 = (T)(sp.k1 * kx);
+    const T xi1 = (T)freq_x(sp, kx);
     const T bdt2 = (T)sp.bdt2, rb = (T)sp.rhobar, s = (T)sp.inv_ntot;
     // beta dt^2 K(xi) + rhobar I with K = N(xi)^T Cbar N(xi), N the Voigt strain of a plane
     // wave.  At fixed (xi1, xi2) it is quadratic in xi3: N = N12 + xi3 E3 (N12 holds the
@@ -677,13 +692,13 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
 #pragma unroll
     for (int j = 0; j < 3; j++) group_fft<L, R, -1>(u[j], t, lds, addr, twL);
     T A0[6], A1[6], A2[6]; // order 00 01 02 11 12 22
-    form(xi1, (T)(sp.k2 * freq_index(ky, sp.n2)), A0, A1, A2);
+    form(xi1, (T)freq_y(sp, ky), A0, A1, A2);
     // per-thread part of r . z in the working precision (24 products at most), summed in
     // FP64 across threads
     T part = 0;
 #pragma unroll
     for (int m = 0; m < R; m++) {
-        const T x3 = (T)(sp.k3 * freq_index(t + m * G, sp.n3));
+        const T x3 = (T)freq_z(sp, t + m * G);
         T K[6];
 #pragma unroll
         for (int q = 0; q < 6; q++) K[q] = A0[q] + x3 * (A1[q] + x3 * A2[q]);
@@ -784,12 +799,19 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
 #endif
     ColAddrT<TXC> addr{c, TX};
     const V* twL = twsm;
-    const T xi1 = (T)(sp.k1 * kx);
+    const T xi1 = (T)freq_x(sp, kx);
     const int n = YAX ? sp.n2 : sp.n3;
     const double kax = YAX ? sp.k2 * sp.inv_n2 : sp.k3 * sp.inv_n3;
     T mul[R];
+    if (sp.mfreq) {
+        const double* mf = sp.mfreq + sp.n1 + (YAX ? 0 : sp.n2);
+        const double inv_n = YAX ? sp.inv_n2 : sp.inv_n3;
 #pragma unroll
-    for (int m = 0; m < R; m++) mul[m] = (T)(kax * freq_index(t + m * G, n));
+        for (int m = 0; m < R; m++) mul[m] = (T)(mf[t + m * G] * inv_n);
+    } else {
+#pragma unroll
+        for (int m = 0; m < R; m++) mul[m] = (T)(kax * freq_index(t + m * G, n));
+    }
 #if NM_COL_OFF32
     auto ld = [&](const V* base, int comp, V (&v)[R]) {
         const char* p = (const char*)(base + comp * cs);

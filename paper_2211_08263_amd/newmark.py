@@ -30,6 +30,7 @@ NM_FP64, NM_FP32 = 0, 1
 PREC_FP64, PREC_MIXED = 0, 1
 ROUTE_AUTO, ROUTE_GREEN, ROUTE_PROJECTED = 0, 1, 2
 WS_COLD, WS_PREV, WS_TAYLOR, WS_LEARNED = 0, 1, 2, 3
+DIFF_SPECTRAL, DIFF_CENTRED2, DIFF_CENTRED4 = 0, 1, 2
 
 EXPORTED = ("nm_newmark_init", "nm_newmark_step", "nm_apply_operator", "nm_precond_apply", "nm_pcg_solve",
             "nm_get_state", "nm_set_state", "nm_state_device_ptrs", "nm_green_matrix", "nm_green_solve",
@@ -51,7 +52,8 @@ class _Problem(C.Structure):
     _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("L", C.c_double * 3), ("n_phases", C.c_int),
                 ("phase_id", C.c_void_p), ("C_voigt", C.c_void_p), ("rho", C.c_void_p),
                 ("gamma_idx", C.c_void_p), ("n_gamma", C.c_int64), ("u0", C.c_void_p), ("v0", C.c_void_p),
-                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double), ("damping", C.c_void_p)]
+                ("dt", C.c_double), ("beta", C.c_double), ("gamma_nm", C.c_double), ("damping", C.c_void_p),
+                ("diff_rule", C.c_int)]
 
 
 class _Options(C.Structure):
@@ -210,8 +212,9 @@ def _c64(a):
 
 def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voigt, rho, gamma_idx, dt: float,
                  beta: float = 0.25, gamma_nm: float = 0.5, u0=None, v0=None, options: Optional[Options] = None,
-                 stream=None, damping=None) -> Context:
-    """damping: per-phase viscous coefficients c >= 0 (force -c v), or None."""
+                 stream=None, damping=None, diff_rule: int = DIFF_SPECTRAL) -> Context:
+    """damping: per-phase viscous coefficients c >= 0 (force -c v), or None; diff_rule: the
+    derivative's symbol (DIFF_SPECTRAL, DIFF_CENTRED2, DIFF_CENTRED4)."""
     lib = load_library()
     nn = [int(x) for x in n] + [1] * (3 - len(n))
     LL = [float(x) for x in L] + [1.0] * (3 - len(L))
@@ -227,7 +230,8 @@ def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voi
     pb = _Problem(int(dim), (C.c_int * 3)(*nn), (C.c_double * 3)(*LL), rh.size, ph.ctypes.data, Cv.ctypes.data,
                   rh.ctypes.data, g.ctypes.data if g.size else None, g.size,
                   None if u0a is None else u0a.ctypes.data, None if v0a is None else v0a.ctypes.data,
-                  float(dt), float(beta), float(gamma_nm), None if dm is None else dm.ctypes.data)
+                  float(dt), float(beta), float(gamma_nm), None if dm is None else dm.ctypes.data,
+                  int(diff_rule))
     o = options or Options()
     gin = None if o.green_in is None else _c64(o.green_in).reshape(-1)
     cb = None
@@ -250,7 +254,8 @@ def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voi
 def newmark_init_problem(pb, options: Optional[Options] = None, u0=None, v0=None, stream=None) -> Context:
     """newmark_init from a workloads.Problem."""
     return newmark_init(pb.dim, pb.n, pb.L, pb.phase_id, pb.C21, pb.rho, pb.gamma_idx, pb.dt, pb.beta, pb.gamma_nm,
-                        u0=u0, v0=v0, options=options, stream=stream, damping=getattr(pb, "damping", None))
+                        u0=u0, v0=v0, options=options, stream=stream, damping=getattr(pb, "damping", None),
+                        diff_rule=getattr(pb, "diff_rule", DIFF_SPECTRAL))
 
 
 def newmark_step(ctx: Context, U, per_point: bool = False) -> dict:

@@ -321,6 +321,7 @@ class Problem:
     n_steps: int = 0
     tol: float = 1e-8
     damping: Optional[np.ndarray] = None  # (n_phases,) viscous coefficients (force -c v), or None
+    diff_rule: int = 0                     # 0 spectral derivative, 1 / 2 centred differences of order 2 / 4
 
     @property
     def n_vox(self) -> int:

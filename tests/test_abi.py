@@ -77,6 +77,7 @@ def _bad_init(**change):
     ("negative damping", "EINVAL"),
     ("non-finite damping", "EINVAL"),
     ("damping in the explicit scheme", "EUNSUPPORTED"),
+    ("unknown differentiation rule", "EINVAL"),
 ])
 def test_init_rejects_bad_arguments(case, code):
     import numpy as np
@@ -100,5 +101,6 @@ def test_init_rejects_bad_arguments(case, code):
         "negative damping": dict(damping=np.array([0.0, -1.0, 0.0, 0.0])),
         "non-finite damping": dict(damping=np.array([0.0, np.nan, 0.0, 0.0])),
         "damping in the explicit scheme": dict(damping=np.array([0.0, 1.0, 0.0, 0.0]), beta=0.0),
+        "unknown differentiation rule": dict(diff_rule=3),
     }[case]
     assert _bad_init(**change) == getattr(nmb, "NM_" + code)
