@@ -1129,12 +1129,51 @@ int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* ph
 #define NM_ZSPEC_BLK32 256
 #endif
 
+// Block sizes of the column passes on 512-long columns: a block holds BLK / G columns of G
+// threads each, so a larger block keeps the rows of a tile wide (coalesced) when G is large.
+// Measured at 512^3 (pass times in us, 256-thread blocks -> these): FP32 z strain 1885 -> 1410,
+// z divergence 1352 -> 1098, y divergence 1050 -> 906, preconditioner y passes 759/765 ->
+// 606/607 and z pass 1544 -> 1086 (radix 16); FP64 z strain 3220 -> 2810, z divergence
+// 2569 -> 2127, preconditioner z pass 2994 -> 2518.  The FP64 y passes stay at 256 (512 was
+// 2-5% slower).  LDS per block: up to 64 KB of exchange buffer plus the twiddle table.
+#ifndef NM_COL512_BLK32
+#define NM_COL512_BLK32 512
+#endif
+#ifndef NM_YPASS512_BLK32
+#define NM_YPASS512_BLK32 512
+#endif
+#ifndef NM_ZSPEC512_BLK32
+#define NM_ZSPEC512_BLK32 512
+#endif
+#ifndef NM_ZSPEC512_BLK64
+#define NM_ZSPEC512_BLK64 512
+#endif
+#ifndef NM_COL512_ZBLK64
+#define NM_COL512_ZBLK64 512
+#endif
+#ifndef NM_YPASS512_BLK64
+#define NM_YPASS512_BLK64 256
+#endif
+#ifndef NM_ZSPEC512_R32
+#define NM_ZSPEC512_R32 16
+#endif
+
 template <int L> constexpr int ypass_radix() { return L >= 16 ? 16 : L; }
+template <typename T, int L> constexpr int ypass_block()
+{
+    return L == 512 ? (sizeof(T) == 4 ? NM_YPASS512_BLK32 : NM_YPASS512_BLK64) : 256;
+}
 template <typename T, int L> constexpr int zspec_radix()
 {
-    return L < 8 ? L : (sizeof(T) == 8 ? (NM_ZSPEC_R64 < L ? NM_ZSPEC_R64 : L) : (NM_ZSPEC_R32 < L ? NM_ZSPEC_R32 : L));
+    return L < 8 ? L
+                 : (sizeof(T) == 8 ? (NM_ZSPEC_R64 < L ? NM_ZSPEC_R64 : L)
+                                   : (L == 512 ? NM_ZSPEC512_R32 : (NM_ZSPEC_R32 < L ? NM_ZSPEC_R32 : L)));
 }
-template <typename T> constexpr int zspec_block() { return sizeof(T) == 8 ? NM_ZSPEC_BLK64 : NM_ZSPEC_BLK32; }
+template <typename T, int L> constexpr int zspec_block()
+{
+    return L == 512 ? (sizeof(T) == 8 ? NM_ZSPEC512_BLK64 : NM_ZSPEC512_BLK32)
+                    : (sizeof(T) == 8 ? NM_ZSPEC_BLK64 : NM_ZSPEC_BLK32);
+}
 
 
 template <typename T>
@@ -1145,20 +1184,21 @@ int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const vo
     NM_SIZE_SWITCH(lay.n2, {
         constexpr int R = ypass_radix<NN>();
         constexpr int G = NN / R;
-        constexpr int TXP = 256 / G;
+        constexpr int BLK = ypass_block<T, NN>();
+        constexpr int TXP = BLK / G;
         const int TX = M >= TXP ? TXP : M;
         dim3 grid(M / TX, n3, ncomp), block(TX * G);
         cx_t<T>* d = (cx_t<T>*)spec;
         if (M >= TXP) {
             if (dir < 0)
-                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, BLK, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
             else
-                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, BLK, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
         } else {
             if (dir < 0)
-                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, BLK, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
             else
-                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, 256, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, BLK, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
         }
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -1176,14 +1216,15 @@ static void zprecond_dispatch(dim3 grid, dim3 block, hipStream_t s, cx_t<T>* spe
 template <typename T> int zprecond_blocks(const SpecParams& sp)
 {
     const int M = sp.n1 / 2;
-    constexpr int BLK = zspec_block<T>();
     if (sp.n3 == 1) {
+        constexpr int BLK = zspec_block<T, 1>();
         const int TX = M < BLK ? M : BLK;
         return (M / TX) * sp.n2;
     }
     int nb = 0;
     [&]() -> int {
         NM_SIZE_SWITCH(sp.n3, {
+            constexpr int BLK = zspec_block<T, NN>();
             constexpr int G = NN / zspec_radix<T, NN>();
             constexpr int TXP = BLK / G;
             nb = (M >= TXP ? M / TXP : 1) * sp.n2;
@@ -1200,12 +1241,13 @@ int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, con
     const int M = sp.n1 / 2;
     const cx_t<T>* t = (const cx_t<T>*)tw;
     cx_t<T>* d = (cx_t<T>*)spec;
-    constexpr int BLK = zspec_block<T>();
     if (sp.n3 == 1) {
+        constexpr int BLK = zspec_block<T, 1>();
         const int TX = M < BLK ? M : BLK;
         zprecond_dispatch<T, 1, BLK, 0>(dim3(M / TX, sp.n2), dim3(TX), s, d, lay, TX, sp, t, partials);
     } else {
         NM_SIZE_SWITCH(sp.n3, {
+            constexpr int BLK = zspec_block<T, NN>();
             constexpr int G = NN / zspec_radix<T, NN>();
             constexpr int TXP = BLK / G;
             if (M >= TXP)
@@ -1233,6 +1275,13 @@ template <typename T, int L> constexpr int colop_radix()
     return L < 16 ? L : (sizeof(T) == 8 ? (NM_COLOP_R64 < L ? NM_COLOP_R64 : L) : 16);
 }
 
+template <typename T, int L, int OP> constexpr int colop_block()
+{
+    return L == 512 ? (sizeof(T) == 4 ? NM_COL512_BLK32
+                                      : ((OP == ZOP_STRAIN || OP == ZOP_DIVZ) ? NM_COL512_ZBLK64 : 256))
+                    : 256;
+}
+
 template <typename T, int L, int TXC>
 static void colop_dispatch(int op, dim3 grid, dim3 block, hipStream_t s, cx_t<T>* S, cx_t<T>* S2, long rowstride,
                            long cs, int TX, const SpecParams& sp, const cx_t<T>* t)
@@ -1241,19 +1290,20 @@ static void colop_dispatch(int op, dim3 grid, dim3 block, hipStream_t s, cx_t<T>
     constexpr bool PF = sizeof(T) == 8 ? NM_COLOP_PF64 : NM_COLOP_PF32;
     switch (op) {
     case YOP_DERIV:
-        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DERIV, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
-                           t);
+        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DERIV, colop_block<T, L, YOP_DERIV>(), TXC, PF>), grid, block, 0, s, S,
+                           S2, rowstride, cs, TX, sp, t);
         break;
     case YOP_DIV:
-        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DIV, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp, t);
+        hipLaunchKernelGGL((k_colop<T, L, R, YOP_DIV, colop_block<T, L, YOP_DIV>(), TXC, PF>), grid, block, 0, s, S, S2,
+                           rowstride, cs, TX, sp, t);
         break;
     case ZOP_STRAIN:
-        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_STRAIN, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
-                           t);
+        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_STRAIN, colop_block<T, L, ZOP_STRAIN>(), TXC, PF>), grid, block, 0, s,
+                           S, S2, rowstride, cs, TX, sp, t);
         break;
     default:
-        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_DIVZ, 256, TXC, PF>), grid, block, 0, s, S, S2, rowstride, cs, TX, sp,
-                           t);
+        hipLaunchKernelGGL((k_colop<T, L, R, ZOP_DIVZ, colop_block<T, L, ZOP_DIVZ>(), TXC, PF>), grid, block, 0, s, S,
+                           S2, rowstride, cs, TX, sp, t);
         break;
     }
 }
@@ -1275,12 +1325,19 @@ int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, v
     } else {
         NM_SIZE_SWITCH(L, {
             constexpr int G = NN / colop_radix<T, NN>();
-            constexpr int TXP = 256 / G;
-            if (M >= TXP)
-                colop_dispatch<T, NN, TXP>(op, dim3(M / TXP, planes), dim3(TXP * G), s, a, b, lay.ps, lay.cs, TXP, sp,
-                                           t);
-            else
+            // y and z operators may take different block sizes (and so tile widths)
+            constexpr int TXY = colop_block<T, NN, YOP_DERIV>() / G;
+            constexpr int TXZ = colop_block<T, NN, ZOP_STRAIN>() / G;
+            if (yax ? M >= TXY : M >= TXZ) {
+                if (yax)
+                    colop_dispatch<T, NN, TXY>(op, dim3(M / TXY, planes), dim3(TXY * G), s, a, b, lay.ps, lay.cs, TXY,
+                                               sp, t);
+                else
+                    colop_dispatch<T, NN, TXZ>(op, dim3(M / TXZ, planes), dim3(TXZ * G), s, a, b, lay.ps, lay.cs, TXZ,
+                                               sp, t);
+            } else {
                 colop_dispatch<T, NN, 0>(op, dim3(1, planes), dim3(M * G), s, a, b, lay.ps, lay.cs, M, sp, t);
+            }
         })
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
