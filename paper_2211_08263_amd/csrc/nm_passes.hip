@@ -1275,11 +1275,19 @@ template <typename T, int L> constexpr int colop_radix()
     return L < 16 ? L : (sizeof(T) == 8 ? (NM_COLOP_R64 < L ? NM_COLOP_R64 : L) : 16);
 }
 
+#ifndef NM_COL256_YBLK32
+#define NM_COL256_YBLK32 256
+#endif
+#ifndef NM_COL256_ZBLK32
+#define NM_COL256_ZBLK32 256
+#endif
 template <typename T, int L, int OP> constexpr int colop_block()
 {
     return L == 512 ? (sizeof(T) == 4 ? NM_COL512_BLK32
                                       : ((OP == ZOP_STRAIN || OP == ZOP_DIVZ) ? NM_COL512_ZBLK64 : 256))
-                    : 256;
+                    : ((L == 256 && sizeof(T) == 4) ? ((OP == ZOP_STRAIN || OP == ZOP_DIVZ) ? NM_COL256_ZBLK32
+                                                                                            : NM_COL256_YBLK32)
+                                                    : 256);
 }
 
 template <typename T, int L, int TXC>
