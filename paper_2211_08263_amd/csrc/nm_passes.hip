@@ -45,6 +45,18 @@
 #ifndef NM_STRESS_PF32
 #define NM_STRESS_PF32 6
 #endif
+// FP64 stress pass on 512-long x lines: one strain component's loads in flight instead of two
+// (measured at 512^3: 4.34 -> 3.17 ms; twiddles from LDS instead of registers 3.38 ms, radix 8
+// 4.07 ms)
+#ifndef NM_STRESS512_TWREG64
+#define NM_STRESS512_TWREG64 NM_STRESS_TWREG64
+#endif
+#ifndef NM_STRESS512_PF64
+#define NM_STRESS512_PF64 1
+#endif
+#ifndef NM_STRESS512_R64
+#define NM_STRESS512_R64 NM_STRESS_R64
+#endif
 
 namespace nm {
 
@@ -431,7 +443,7 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
     const bool valid = line < (long)lay.n2 * lay.n3;
     LineAddr<R, (int)sizeof(V)> addr{ll * LP};
     // the twelve transforms share their twiddles: with TWR they are read once into registers
-    constexpr bool TWR = sizeof(T) == 8 ? NM_STRESS_TWREG64 : NM_STRESS_TWREG32;
+    constexpr bool TWR = sizeof(T) == 8 ? (N1 == 512 ? NM_STRESS512_TWREG64 : NM_STRESS_TWREG64) : NM_STRESS_TWREG32;
     TwRegs<M, R, V> twr;
     V twn[R];
     if constexpr (TWR) {
@@ -455,7 +467,7 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
     // keep the global loads of the next PF strain components in flight while a
     // component is transformed: the fences of the LDS exchanges would otherwise hold
     // each component's loads back until the previous transform is done
-    constexpr int PFQ = sizeof(T) == 8 ? NM_STRESS_PF64 : NM_STRESS_PF32;
+    constexpr int PFQ = sizeof(T) == 8 ? (N1 == 512 ? NM_STRESS512_PF64 : NM_STRESS_PF64) : NM_STRESS_PF32;
     constexpr int PF = PFQ < 6 ? PFQ : 6;
     V raw[6][R];
 #pragma unroll
@@ -1102,7 +1114,7 @@ int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* ph
     const cx_t<T>* t = (const cx_t<T>*)tw;
     NM_SIZE_SWITCH(n1, {
         constexpr int M = NN / 2;
-        constexpr int RQ = sizeof(T) == 8 ? NM_STRESS_R64 : NM_STRESS_R32;
+        constexpr int RQ = sizeof(T) == 8 ? (NN == 512 ? NM_STRESS512_R64 : NM_STRESS_R64) : NM_STRESS_R32;
         constexpr int R0 = M >= RQ ? RQ : M;
         constexpr int R = R0 * 64 >= M ? R0 : M / 64; // a line stays inside one wavefront
         constexpr int G = M / R, LPB = kBlock / G;
