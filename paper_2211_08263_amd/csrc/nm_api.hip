@@ -76,6 +76,7 @@ struct nm_ctx {
     bool pred_ready = false; // ut and b hold the predictor of the coming step (and winc its scale sums)
     double* winc = nullptr;  // per-block sums of |u~ - u_n|^2 from the fused corrector
     bool d32_is_x = false;   // d32 holds the FP32 copy of the initial iterate (learned start)
+    long ws_rejected = 0;    // steps whose learned iterate was replaced by the zero start
     uint16_t* sfeat = nullptr; // unscaled BF16 state features [N][16] of the learned start
     hipEvent_t ev_warm[2] = {nullptr, nullptr}; // brackets the learned start on the stream (timing only)
     bool sfeat_ready = false;  // sfeat was written by the last fused corrector
@@ -480,7 +481,10 @@ int lift_bref(nm_ctx* c, const double* U3, double* bref)
 constexpr double kSmallUpdate = 5e3;
 
 // rr_known >= 0: c->r already holds the first sweep's residual P (b - A x), r.r = rr_known.
-int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_known = -1.0)
+// rejected (or null): set, and nothing solved, when the initial iterate's residual exceeds
+// bref (the zero start's), so that the caller can restart from the zero start.
+int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_known = -1.0,
+                bool* rejected = nullptr)
 {
     hipStream_t s = c->stream;
     const long n = 3 * c->N;
@@ -524,6 +528,10 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
             CHK(read_scalars(c));
             rr = c->hscal[S_RR];
             approx = true;
+            if (rejected && rr > bref * bref) {
+                *rejected = true;
+                return NM_OK;
+            }
         } else {
             CHK(apply_A<double>(c, x, c->q, c->mask));
             LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s, c->r32));
@@ -1185,9 +1193,27 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         if (c->lift && !per_point) CHK(lift_bref(c, U3.data(), &bref));
         else CHK(projected_bref(c, c->w, &bref));
         // the zero start is u_bar itself, so its initial residual is r_bar
-        const double rr0 = c->opt.warm_start == NM_WS_COLD ? bref * bref : -1.0;
+        double rr0 = c->opt.warm_start == NM_WS_COLD ? bref * bref : -1.0;
+        // a learned iterate whose residual exceeds the zero start's is replaced by the zero
+        // start (u_bar, residual r_bar), so the learned start never begins further away
+        const bool guard = c->opt.warm_start == NM_WS_LEARNED;
+        auto restart_from_zero = [&]() -> int {
+            LCHK(c, launch_fill<double>(c->w, 0.0, n, s));
+            if (c->ng > 0) LCHK(c, launch_set_gamma(c->w, c->gidx, c->ng, c->Ubuf, per_point, 3, c->N, s));
+            c->d32_is_x = false;
+            if (c->lift && !per_point) CHK(lift_bref(c, U3.data(), &bref));
+            else CHK(projected_bref(c, c->w, &bref));
+            rr0 = bref * bref;
+            c->ws_rejected++;
+            return NM_OK;
+        };
         if (c->opt.precision == NM_PREC_MIXED) {
-            CHK(solve_mixed(c, c->w, bref, &local, rr0));
+            bool rejected = false;
+            CHK(solve_mixed(c, c->w, bref, &local, rr0, guard ? &rejected : nullptr));
+            if (rejected) {
+                CHK(restart_from_zero());
+                CHK(solve_mixed(c, c->w, bref, &local, rr0));
+            }
             if (c->opt.true_residual) {
                 CHK(apply_A<double>(c, c->w, c->q, c->mask));
                 LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
@@ -1196,6 +1222,15 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
                 local.relres = std::sqrt(c->hscal[S_RR]) / (bref > 0 ? bref : 1.0);
             }
         } else {
+            if (guard) {
+                // residual of the learned iterate, kept in c->r for the solve unless rejected
+                CHK(apply_A<double>(c, c->w, c->q, c->mask));
+                LCHK(c, launch_residual<double>(c->b, c->q, c->r, c->mask, c->N, 3, c->part_a, s));
+                LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+                CHK(read_scalars(c));
+                rr0 = c->hscal[S_RR];
+                if (rr0 > bref * bref) CHK(restart_from_zero());
+            }
             PcgResult r1;
             CHK(pcg<double>(c, c->b, c->w, c->r, c->p, c->q, true, false, bref, c->opt.tol, c->opt.max_iter,
                             -1, false, &r1, rr0));
