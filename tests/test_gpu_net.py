@@ -447,3 +447,38 @@ def test_trained_start_on_a_held_out_trajectory():
     assert res["learned"]["relres0"] < 0.8 * res["cold"]["relres0"]
     assert res["learned"]["relres0"] < 0.8 * res["prev"]["relres0"]
     assert res["learned"]["iters"] <= res["cold"]["iters"]
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_start_worse_than_zero_is_replaced_by_the_zero_start(precision):
+    """A network that predicts nonsense (random weights scaled by 100): the step compares the
+    learned iterate's projected residual with the zero start's and restarts from the zero
+    start when it is larger, so no step starts further away than the zero start does, the
+    iteration counts are the zero start's and the trajectory agrees with it to the tolerance."""
+    pb = W.make_polycrystal(n=32, n_grains=8, seed=1007, n_steps=10)
+    net = nmb.Net(seed=5)
+    net.set_params(net.get_params() * 100.0)
+    prec = nmb.PREC_MIXED if precision == "mixed" else nmb.PREC_FP64
+    res = {}
+    for name, ws in (("cold", nmb.WS_COLD), ("learned", nmb.WS_LEARNED)):
+        opts = nmb.Options(tol=1e-9, max_iter=500, warm_start=ws, precision=prec, true_residual=True)
+        with nmb.newmark_init_problem(pb, opts) as ctx:
+            if ws == nmb.WS_LEARNED:
+                nmb.ws_attach(ctx, net)
+            st, us = [], []
+            for s in range(8):
+                st.append(nmb.newmark_step(ctx, pb.U(s + 1)))
+                us.append(nmb.get_state(ctx)["u"].copy())
+        res[name] = (st, us)
+    net.close()
+    key = "inner_iters" if precision == "mixed" else "iters"
+    it = {k: [x[key] if precision == "mixed" else x[key][0] for x in v[0]] for k, v in res.items()}
+    r0 = [x["relres0"] for x in res["learned"][0]]
+    err = max(np.linalg.norm(a - b) / max(np.linalg.norm(a), 1e-300)
+              for a, b in zip(res["cold"][1], res["learned"][1]) if np.abs(a).max() > 0)
+    print(f"{precision}: nonsense network, initial residuals {np.round(r0, 6).tolist()}, iterations "
+          f"{it['learned']} (zero start {it['cold']}), rel L2 to the zero-start run {err:.2e}", flush=True)
+    assert all(r <= 1.0 + 1e-6 for r in r0)
+    assert all(abs(a - b) <= 1 for a, b in zip(it["learned"], it["cold"]))
+    assert max(x["relres"] for x in res["learned"][0]) <= 1e-9
+    assert err <= 1e-7
