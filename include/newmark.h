@@ -108,8 +108,13 @@ typedef struct nm_options {
                                  the unit-force solves (section 3.2: the preprocessing of an RVE can be
                                  stored and reused), or NULL; host, copied */
     void (*green_progress)(int64_t done, int64_t total, void* user); /* GREEN route: called after each
-                                 unit-force solve of nm_newmark_init (may be NULL) */
+                                 unit-force solve of nm_newmark_init, or each group solved together
+                                 (may be NULL) */
     void* green_progress_user;
+    int green_batch;          /* GREEN route: unit-force solves run together through one chain of kernels
+                                 (FP64, each giving the column a single solve gives): 0 picks the number
+                                 from the grid (about 8M voxels of work, at most 16), 1 solves one at a
+                                 time in the context's precision, k >= 2 solves k at a time (at most 64) */
 } nm_options;
 
 typedef struct nm_step_stats {

@@ -86,6 +86,12 @@ struct nm_ctx {
     int* pivdev = nullptr;         // row swaps of the factorization
     int* singdev = nullptr;        // set by the factorization on a zero pivot
     int green_sweeps = 0, green_inner = 0; // mixed-precision Green route: running totals
+    // several unit-force solves at once (Green route preprocessing): fields [b][3][N] and
+    // spectra [b][6 cs] of up to mnb solves, their partial sums and scalar blocks
+    int mnb = 0;
+    double *mX = nullptr, *mR = nullptr, *mP = nullptr, *mQ = nullptr, *mU = nullptr;
+    double2 *mS = nullptr, *mS2 = nullptr;
+    double *mpa = nullptr, *mpb = nullptr, *mscal = nullptr, *mhscal = nullptr;
     // explicit central-difference scheme (beta == 0)
     bool explicit_scheme = false;
     double* Fdev = nullptr;      // dim * max(ng, 1): the Gamma force of the last explicit step
@@ -149,6 +155,19 @@ template <typename T> int dalloc(nm_ctx* c, T** ptr, size_t count)
     c->allocs.push_back(p);
     *ptr = (T*)p;
     return NM_OK;
+}
+
+// Release a buffer from dalloc before the context ends.
+template <typename T> void dfree(nm_ctx* c, T** ptr)
+{
+    if (!*ptr) return;
+    for (size_t i = 0; i < c->allocs.size(); i++)
+        if (c->allocs[i] == (void*)*ptr) {
+            (void)hipFree(*ptr);
+            c->allocs.erase(c->allocs.begin() + i);
+            break;
+        }
+    *ptr = nullptr;
 }
 
 bool pow2_in(int n, int lo, int hi) { return n >= lo && n <= hi && (n & (n - 1)) == 0; }
@@ -619,6 +638,136 @@ int green_solve(nm_ctx* c, const double* rhs, double* x, double bref, double tol
     return pcg<double>(c, rhs, x, c->r, c->p, c->q, false, x_zero, bref, tol, c->opt.max_iter, -1, false, res);
 }
 
+// Fields solved together by the Green route's unit-force solves: enough to give the kernels
+// about 8M voxels of work (small grids are bound by launches, not by memory traffic), at most
+// 16; options.green_batch overrides (1: one at a time).  0 when the launch layout does not
+// keep every field's partial sums apart.
+int green_batch_size(nm_ctx* c)
+{
+    int nb = c->opt.green_batch;
+    if (nb <= 0) {
+        nb = 1;
+        while (nb < 16 && (long)nb * 2 * c->N <= (8L << 20)) nb *= 2;
+    }
+    if (nb > 64) nb = 64;
+    const long lpf = 3L * c->n2 * c->n3;
+    if (nb < 2 || (long)xfwd_blocks(c->n1, nb * lpf) != (long)nb * xfwd_blocks(c->n1, lpf) ||
+        (long)xinv_blocks(c->n1, nb * lpf) != (long)nb * xinv_blocks(c->n1, lpf))
+        return 1;
+    return nb;
+}
+
+// nb independent unmasked FP64 solves A x_b = r_b from x_b = 0 through one chain of kernels:
+// c->mR holds the right-hand sides on entry (then the residuals), c->mX receives the
+// solutions; each loop stops on ||r_b|| <= tol ||rhs_b|| and is frozen from then on (the
+// multi-loop reductions), so that every solution is the one a single solve gives.
+int pcg_multi(nm_ctx* c, int nb, double tol, int* iters_max)
+{
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    const long lpf = 3L * c->n2 * c->n3;
+    const long bs = 6 * c->lay.cs;
+    SpecLayout lay3 = c->lay;
+    lay3.stop = nullptr;
+    lay3.nb = nb;
+    lay3.bc = 3;
+    lay3.bs = bs;
+    SpecLayout lay6 = lay3;
+    lay6.bc = 1;
+    SpecParams sp = c->sp;
+    sp.stop = nullptr;
+    sp.bs = bs;
+    sp.bk = nb;
+    const int nbx = xinv_blocks(c->n1, lpf), nbf = xfwd_blocks(c->n1, lpf), nbz = zprecond_blocks<double>(c->sp);
+    const double2* tw = c->tw64;
+    // r.r of each right-hand side (the zero start's residual) and the loop thresholds
+    std::vector<double> thr2(nb);
+    for (int b = 0; b < nb; b++) {
+        LCHK(c, launch_dot<double>(c->mR + b * n, c->mR + b * n, n, c->part_a, s));
+        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->mscal + b * S_COUNT, RED_STORE_RR, 0, s));
+    }
+    HIPCHK(c, hipMemcpyAsync(c->mhscal, c->mscal, nb * S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+    HIPCHK(c, hipStreamSynchronize(s));
+    for (int b = 0; b < nb; b++) {
+        const double rr = c->mhscal[b * S_COUNT + S_RR];
+        if (!(rr > 0) || !std::isfinite(rr)) return fail(c, NM_EINVAL, "unit-force right-hand side %d is zero", b);
+        thr2[b] = tol * tol * rr;
+        LCHK(c, launch_loop_init(c->mscal + b * S_COUNT, thr2[b], c->opt.max_iter, 0, s));
+    }
+    LCHK(c, launch_fill<double>(c->mX, 0.0, nb * n, s));
+    // z = M r as its x spectrum, r.z
+    XFwdArgs fa{};
+    fa.spec = c->mS;
+    fa.lay = lay3;
+    fa.scal = c->mscal;
+    fa.nlines = nb * lpf;
+    fa.lines_per_batch = lpf;
+    fa.src = c->mR;
+    LCHK(c, launch_xfwd<double>(XF_PLAIN, c->n1, fa, tw, s));
+    LCHK(c, launch_ypass<double>(-1, 3 * nb, lay3, c->mS, tw, s));
+    LCHK(c, launch_zprecond<double>(sp, lay3, c->mS, tw, s, c->mpb));
+    LCHK(c, launch_ypass<double>(+1, 3 * nb, lay3, c->mS, tw, s));
+    LCHK(c, launch_reduce_multi(c->mpb, nbz, nb, c->mscal, RED_RZ_INIT, s));
+    XInvArgs pa = xi_args(c, c->mS, nullptr, nullptr, nullptr, nullptr, nullptr);
+    pa.lay = lay3;
+    pa.nlines = nb * lpf;
+    pa.lines_per_batch = lpf;
+    pa.p = c->mP;
+    pa.x = c->mX;
+    pa.scal = c->mscal;
+    XInvArgs ia = xi_args(c, c->mS, c->mQ, c->mP, c->rho64, nullptr, c->mpb);
+    ia.lay = lay3;
+    ia.nlines = nb * lpf;
+    ia.lines_per_batch = lpf;
+    XFwdArgs fu = fa;
+    fu.src = nullptr;
+    fu.r = c->mR;
+    fu.q = c->mQ;
+    fu.partials = c->mpa;
+    int it = 0;
+    for (;;) {
+        for (int k = 0; k < 4; k++) {
+            // p = z + beta p (x += alpha p_old); q = A p; alpha
+            LCHK(c, launch_xpupdate<double>(c->n1, pa, tw, s));
+            LCHK(c, launch_colop<double>(YOP_DERIV, sp, lay3, c->mS, c->mS2, tw, s));
+            LCHK(c, launch_colop<double>(ZOP_STRAIN, sp, lay3, c->mS, c->mS2, tw, s));
+            LCHK(c, launch_xstress<double>(c->n1, c->mS2, lay6, c->phase, c->C64, tw, s));
+            LCHK(c, launch_colop<double>(YOP_DIV, sp, lay3, c->mS, c->mS2, tw, s));
+            LCHK(c, launch_colop<double>(ZOP_DIVZ, sp, lay3, c->mS, c->mS2, tw, s));
+            LCHK(c, launch_xinv<double>(XI_OPERATOR, c->n1, ia, tw, s));
+            LCHK(c, launch_reduce_multi(c->mpb, nbx, nb, c->mscal, RED_ALPHA, s));
+            // r -= alpha q, r.r (stop test); z = M r, r.z; beta
+            LCHK(c, launch_xfwd<double>(XF_UPDATE, c->n1, fu, tw, s));
+            LCHK(c, launch_reduce_multi(c->mpa, nbf, nb, c->mscal, RED_RR_CHECK, s));
+            LCHK(c, launch_ypass<double>(-1, 3 * nb, lay3, c->mS, tw, s));
+            LCHK(c, launch_zprecond<double>(sp, lay3, c->mS, tw, s, c->mpb));
+            LCHK(c, launch_ypass<double>(+1, 3 * nb, lay3, c->mS, tw, s));
+            LCHK(c, launch_reduce_multi(c->mpb, nbz, nb, c->mscal, RED_BETA, s));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->mhscal, c->mscal, nb * S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        bool all = true;
+        it = 0;
+        for (int b = 0; b < nb; b++) {
+            const double* h = c->mhscal + b * S_COUNT;
+            if (!std::isfinite(h[S_RR])) return fail(c, NM_ENAN, "non-finite residual in unit-force solve %d", b);
+            all = all && h[S_STOP] != 0.0;
+            it = std::max(it, (int)h[S_ITER]);
+        }
+        if (all) break;
+    }
+    // the deferred last x += alpha p (alpha is zero for the loops frozen before the last
+    // iteration, which received it already)
+    for (int b = 0; b < nb; b++) {
+        if (!(c->mhscal[b * S_COUNT + S_RR] <= thr2[b]))
+            return fail(c, NM_ENOTCONV, "unit-force solve did not reach tol %.3g in %d iterations", tol,
+                        (int)c->mhscal[b * S_COUNT + S_ITER]);
+        LCHK(c, launch_axpy_scal<double>(c->mX + b * n, c->mP + b * n, c->mscal + b * S_COUNT + S_ALPHA, n, s));
+    }
+    if (iters_max) *iters_max = it;
+    return NM_OK;
+}
+
 // G from the unit-force solves of eq. (solve_green): column d p + j is the Gamma trace of
 // A^-1 (e_j at x_p), rows ordered d q + i; written into the device matrix column by column
 // (no host round trip per column).  With a stored G (row major, as nm_green_matrix returns
@@ -643,6 +792,54 @@ int build_green(nm_ctx* c, const double* G_in)
             }
         std::memcpy(c->G.data(), G_in, c->G.size() * sizeof(double));
         HIPCHK(c, hipMemcpy(c->Gdev, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice));
+    } else if (int nb = green_batch_size(c); nb >= 2) {
+        // nb unit-force solves at a time (FP64), each column as a single solve would give it
+        if (c->mnb < nb) {
+            const long cs = c->lay.cs;
+            const int npa = xfwd_blocks(c->n1, 3L * c->n2 * c->n3);
+            const int npb = std::max(xinv_blocks(c->n1, 3L * c->n2 * c->n3), zprecond_blocks<double>(c->sp));
+            CHK(dalloc(c, &c->mX, nb * n));
+            CHK(dalloc(c, &c->mR, nb * n));
+            CHK(dalloc(c, &c->mP, nb * n));
+            CHK(dalloc(c, &c->mQ, nb * n));
+            CHK(dalloc(c, &c->mU, 3 * (size_t)nb));
+            CHK(dalloc(c, &c->mS, nb * 6 * cs));
+            CHK(dalloc(c, &c->mS2, nb * 6 * cs));
+            CHK(dalloc(c, &c->mpa, (size_t)nb * npa));
+            CHK(dalloc(c, &c->mpb, (size_t)nb * npb));
+            CHK(dalloc(c, &c->mscal, (size_t)nb * S_COUNT));
+            HIPCHK(c, hipHostMalloc((void**)&c->mhscal, nb * S_COUNT * sizeof(double), hipHostMallocDefault));
+            c->mnb = nb;
+        }
+        std::vector<double> units(3 * (size_t)nb);
+        for (long col0 = 0; col0 < nd; col0 += nb) {
+            const int kk = (int)std::min<long>(nb, nd - col0);
+            LCHK(c, launch_fill<double>(c->mR, 0.0, kk * n, s));
+            std::fill(units.begin(), units.end(), 0.0);
+            for (int b = 0; b < kk; b++) units[3 * b + (col0 + b) % d] = 1.0;
+            HIPCHK(c, hipMemcpyAsync(c->mU, units.data(), 3 * kk * sizeof(double), hipMemcpyHostToDevice, s));
+            for (int b = 0; b < kk; b++)
+                LCHK(c, launch_set_gamma(c->mR + b * n, c->gidx + (col0 + b) / d, 1, c->mU + 3 * b, 0, 3, c->N, s));
+            int its = 0;
+            CHK(pcg_multi(c, kk, c->opt.green_tol, &its));
+            for (int b = 0; b < kk; b++) {
+                LCHK(c, launch_gather_gamma(c->gbuf, c->mX + b * n, c->gidx, c->ng, 3, c->N, s));
+                LCHK(c, launch_green_column(c->Gdev, nd, col0 + b, c->gbuf, c->ng, d, s));
+            }
+            HIPCHK(c, hipStreamSynchronize(s));
+            if (c->opt.green_progress) c->opt.green_progress(col0 + kk, nd, c->opt.green_progress_user);
+        }
+        // the solve buffers are needed only here
+        for (double** f : {&c->mX, &c->mR, &c->mP, &c->mQ, &c->mU, &c->mpa, &c->mpb, &c->mscal}) dfree(c, f);
+        dfree(c, &c->mS);
+        dfree(c, &c->mS2);
+        (void)hipHostFree(c->mhscal);
+        c->mhscal = nullptr;
+        c->mnb = 0;
+        std::vector<double> cm((size_t)nd * nd);
+        HIPCHK(c, hipMemcpy(cm.data(), c->Gdev, cm.size() * sizeof(double), hipMemcpyDeviceToHost));
+        for (long i = 0; i < nd; i++)
+            for (long j = 0; j < nd; j++) c->G[(size_t)i * nd + j] = cm[(size_t)j * nd + i];
     } else {
         double unit[3];
         for (long pnt = 0; pnt < c->ng; pnt++)
@@ -803,6 +1000,7 @@ void nm_destroy(nm_ctx* c)
         if (e) (void)hipEventDestroy(e);
     for (void* p : c->allocs) (void)hipFree(p);
     if (c->hscal) (void)hipHostFree(c->hscal);
+    if (c->mhscal) (void)hipHostFree(c->mhscal);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     delete c;
 }

@@ -21,6 +21,10 @@ struct SpecParams {
     // derivative uses in place of the spectral xi (n1 + n2 + n3 entries, axis after axis, indexed
     // by bin), or null for the spectral derivative.
     const double* mfreq = nullptr;
+    // Several independent fields at once (multi-right-hand-side solves): bk fields whose
+    // spectra lie bs elements apart; the column passes take the field from blockIdx.z.
+    long bs = 0;
+    int bk = 1;
 };
 
 
@@ -34,11 +38,17 @@ struct SpecLayout {
     long ps;        // kz (plane) stride, >= n2 * M
     long cs;        // component stride, >= n3 * ps
     const double* stop = nullptr; // device flag: when non-zero, kernels given this layout exit at once
+    // Several fields at once: nb fields of bc components each, bs elements apart (bc == 0: one
+    // field, components cs apart).
+    int nb = 1;
+    int bc = 0;
+    long bs = 0;
+    __host__ __device__ __forceinline__ long comp(long c) const { return bc ? (c / bc) * bs + (c % bc) * cs : c * cs; }
     __host__ __device__ __forceinline__ long line(long l) const
     {
         // x line l = (component, kz, ky) in row-major order
         const long yz = l % ((long)n2 * n3), c = l / ((long)n2 * n3);
-        return c * cs + (yz >> log2n2) * ps + (yz & (n2 - 1)) * (long)M;
+        return comp(c) + (yz >> log2n2) * ps + (yz & (n2 - 1)) * (long)M;
     }
 };
 
@@ -83,6 +93,7 @@ struct XFwdArgs {
     void* spec;           // output half spectrum
     SpecLayout lay;
     long nlines;          // number of x lines (components x n2 x n3)
+    long lines_per_batch = 0; // several fields: x lines per field (their device scalars lie S_COUNT apart)
 };
 
 struct XInvArgs {
@@ -101,6 +112,7 @@ struct XInvArgs {
     void* x = nullptr;            // launch_xpupdate: iterate (in/out); XI_EXPLICIT: acceleration (in/out)
     double dt = 0.0;              // XI_EXPLICIT: time increment
     const double* scal = nullptr; // launch_xpupdate: device scalars (alpha, beta, first)
+    long lines_per_batch = 0;     // several fields: x lines per field (their scalars lie S_COUNT apart)
 };
 
 // Number of blocks a launch uses (sizes the partials array).

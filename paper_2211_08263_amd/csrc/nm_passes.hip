@@ -169,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
             }
         } else {
             // r -= alpha q and the partial sums of r.r
-            const T alpha = (T)a.scal[S_ALPHA];
+            const T alpha = (T)a.scal[(a.lines_per_batch ? line / a.lines_per_batch : 0) * S_COUNT + S_ALPHA];
             V* r = (V*)a.r + off;
             const V* q = (const V*)a.q + off;
 #pragma unroll
@@ -274,7 +274,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
             for (int m = 0; m < R; m++) out[t + m * G] = v[m];
         } else if constexpr (MODE == XI_EXPLICIT) {
             // o = dt/2 div sigma: v <- v + dt/2 a + o / rho, a <- (2/dt) o / rho
-            const bool zero_comp = (a.dim == 2) && (line / a.lines_per_comp == 2);
+            const bool zero_comp = (a.dim == 2) && ((line / a.lines_per_comp) % 3 == 2);
             const T* rho = (const T*)a.rho;
             const T hdt = (T)(0.5 * a.dt), idt2 = (T)(2.0 / a.dt);
             V* vp = (V*)a.p + off;
@@ -294,7 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
                 ap[n] = an;
             }
         } else {
-            const bool zero_comp = (a.dim == 2) && (line / a.lines_per_comp == 2);
+            const bool zero_comp = (a.dim == 2) && ((line / a.lines_per_comp) % 3 == 2);
             const T* rho = (const T*)a.rho;
 #pragma unroll
             for (int m = 0; m < R; m++) {
@@ -347,9 +347,10 @@ __global__ __launch_bounds__(kBlock) void k_xpupdate(XInvArgs a, const cx_t<T>* 
 #pragma unroll
     for (int m = 0; m < R; m++) v[m] = valid ? spec[soff + t + m * G] : V{0, 0};
     // the real-space operands are fetched before the transforms
-    const bool first = a.scal[S_FIRST] != 0.0;
-    const T beta = (T)a.scal[S_BETA];
-    const T alpha = (T)a.scal[S_ALPHA];
+    const double* sc = a.scal + ((a.lines_per_batch && valid) ? line / a.lines_per_batch : 0) * S_COUNT;
+    const bool first = sc[S_FIRST] != 0.0;
+    const T beta = (T)sc[S_BETA];
+    const T alpha = (T)sc[S_ALPHA];
     V* p = (V*)a.p + off;
     V* x = (V*)a.x + off;
     V po[R], xo[R];
@@ -374,7 +375,7 @@ __global__ __launch_bounds__(kBlock) void k_xpupdate(XInvArgs a, const cx_t<T>* 
     }
     group_sync<true>();
     group_fft<M, R, +1, true>(v, t, lds, addr, twM);
-    const bool zero_comp = (a.dim == 2) && (line / a.lines_per_comp == 2);
+    const bool zero_comp = (a.dim == 2) && ((line / a.lines_per_comp) % 3 == 2);
 #pragma unroll
     for (int m = 0; m < R; m++) {
         V z = v[m];
@@ -440,7 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
     const V* twN = twsm + M;
     const int tid = threadIdx.x, ll = tid / G, t = tid % G;
     const long line = (long)blockIdx.x * LPB + ll;
-    const bool valid = line < (long)lay.n2 * lay.n3;
+    const long lpf = (long)lay.n2 * lay.n3; // x lines per component of one field
+    const bool valid = line < lpf * lay.nb;
     LineAddr<R, (int)sizeof(V)> addr{ll * LP};
     // the twelve transforms share their twiddles: with TWR they are read once into registers
     constexpr bool TWR = sizeof(T) == 8 ? (N1 == 512 ? NM_STRESS512_TWREG64 : NM_STRESS_TWREG64) : NM_STRESS_TWREG32;
@@ -476,7 +478,7 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
         for (int m = 0; m < R; m++) raw[c][m] = valid ? spec[c * NS + off + t + m * G] : V{0, 0};
     uint32_t phw[R];
     {
-        const uint32_t* ph2 = (const uint32_t*)phase + (valid ? line : 0) * M;
+        const uint32_t* ph2 = (const uint32_t*)phase + (valid ? line % lpf : 0) * M;
 #pragma unroll
         for (int m = 0; m < R; m++) phw[m] = ph2[t + m * G];
     }
@@ -559,7 +561,7 @@ template <int TXC> struct ColAddrT {
 
 template <typename T, int L, int R, int DIR, int BLK, int TXC>
 __global__ __launch_bounds__(BLK) void k_ypass(cx_t<T>* __restrict__ data, long colstride, long planestride, long cs,
-                                               int TXr, const cx_t<T>* __restrict__ tw, const double* stop)
+                                               int TXr, const cx_t<T>* __restrict__ tw, const double* stop, long bs)
 {
     if (stopped(stop)) return;
     using V = cx_t<T>;
@@ -570,7 +572,9 @@ __global__ __launch_bounds__(BLK) void k_ypass(cx_t<T>* __restrict__ data, long 
     stage_twiddles<L>(twsm, tw);
     __syncthreads();
     const int tid = threadIdx.x, c = tid % TX, t = tid / TX;
-    V* col = data + blockIdx.z * cs + blockIdx.y * planestride + (long)blockIdx.x * TX + c;
+    // component blockIdx.z (of three per field when several fields lie bs apart)
+    const long zc = bs ? (long)(blockIdx.z / 3) * bs + (long)(blockIdx.z % 3) * cs : (long)blockIdx.z * cs;
+    V* col = data + zc + blockIdx.y * planestride + (long)blockIdx.x * TX + c;
     V v[R];
 #pragma unroll
     for (int m = 0; m < R; m++) v[m] = col[(long)(t + m * G) * colstride];
@@ -621,7 +625,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     const int M = sp.n1 / 2;
     const int kx = blockIdx.x * TX + c, ky = blockIdx.y;
     // uniform column-tile base (scalar registers) plus 32-bit per-lane byte offsets
-    V* const cb = data + (long)ky * M + (long)blockIdx.x * TX;
+    V* const cb = data + (long)blockIdx.z * sp.bs + (long)ky * M + (long)blockIdx.x * TX;
     const uint32_t lane = (uint32_t)(c * sizeof(V)) + (uint32_t)t * (uint32_t)(colstride * sizeof(V));
     const uint32_t mstep = (uint32_t)(G * colstride * sizeof(V));
     auto at = [&](int j, int m) -> V& { return *(V*)((char*)(cb + j * NS) + (lane + (uint32_t)m * mstep)); };
@@ -768,7 +772,8 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
             if (threadIdx.x == 0)
                 for (int i = 0; i < (int)blockDim.x; i++) tot += red1[i];
         }
-        if (threadIdx.x == 0) partials[(long)blockIdx.y * gridDim.x + blockIdx.x] = tot;
+        if (threadIdx.x == 0)
+            partials[((long)blockIdx.z * gridDim.y + blockIdx.y) * gridDim.x + blockIdx.x] = tot;
     }
 }
 
@@ -801,13 +806,14 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
     const long step = YAX ? (long)M : rowstride;
 #if NM_COL_OFF32
     // uniform tile bases (scalar registers) plus 32-bit per-lane byte offsets
-    V* const s1 = S + start + (long)blockIdx.x * TX;
-    V* const s2 = S2 + start + (long)blockIdx.x * TX;
+    // several fields at once: field blockIdx.z, spectra sp.bs elements apart
+    V* const s1 = S + (long)blockIdx.z * sp.bs + start + (long)blockIdx.x * TX;
+    V* const s2 = S2 + (long)blockIdx.z * sp.bs + start + (long)blockIdx.x * TX;
     const uint32_t lane = (uint32_t)(c * sizeof(V)) + (uint32_t)t * (uint32_t)(step * sizeof(V));
     const uint32_t mstep = (uint32_t)(G * step * sizeof(V));
 #else
-    V* s1 = S + start + kx;
-    V* s2 = S2 + start + kx;
+    V* s1 = S + (long)blockIdx.z * sp.bs + start + kx;
+    V* s2 = S2 + (long)blockIdx.z * sp.bs + start + kx;
 #endif
     ColAddrT<TXC> addr{c, TX};
     const V* twL = twsm;
@@ -1110,7 +1116,7 @@ template <typename T>
 int launch_xstress(int n1, void* spec, const SpecLayout& lay, const uint16_t* phase, const void* C21, const void* tw,
                    hipStream_t s)
 {
-    const long lpc = (long)lay.n2 * lay.n3;
+    const long lpc = (long)lay.n2 * lay.n3 * lay.nb;
     const cx_t<T>* t = (const cx_t<T>*)tw;
     NM_SIZE_SWITCH(n1, {
         constexpr int M = NN / 2;
@@ -1203,14 +1209,14 @@ int launch_ypass(int dir, int ncomp, const SpecLayout& lay, void* spec, const vo
         cx_t<T>* d = (cx_t<T>*)spec;
         if (M >= TXP) {
             if (dir < 0)
-                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, BLK, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, BLK, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop, lay.bs);
             else
-                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, BLK, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, BLK, TXP>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop, lay.bs);
         } else {
             if (dir < 0)
-                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, BLK, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, -1, BLK, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop, lay.bs);
             else
-                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, BLK, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop);
+                hipLaunchKernelGGL((k_ypass<T, NN, R, +1, BLK, 0>), grid, block, 0, s, d, (long)M, lay.ps, lay.cs, TX, t, lay.stop, lay.bs);
         }
     })
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -1256,17 +1262,17 @@ int launch_zprecond(const SpecParams& sp, const SpecLayout& lay, void* spec, con
     if (sp.n3 == 1) {
         constexpr int BLK = zspec_block<T, 1>();
         const int TX = M < BLK ? M : BLK;
-        zprecond_dispatch<T, 1, BLK, 0>(dim3(M / TX, sp.n2), dim3(TX), s, d, lay, TX, sp, t, partials);
+        zprecond_dispatch<T, 1, BLK, 0>(dim3(M / TX, sp.n2, sp.bk), dim3(TX), s, d, lay, TX, sp, t, partials);
     } else {
         NM_SIZE_SWITCH(sp.n3, {
             constexpr int BLK = zspec_block<T, NN>();
             constexpr int G = NN / zspec_radix<T, NN>();
             constexpr int TXP = BLK / G;
             if (M >= TXP)
-                zprecond_dispatch<T, NN, BLK, TXP>(dim3(M / TXP, sp.n2), dim3(TXP * G), s, d, lay, TXP, sp, t,
+                zprecond_dispatch<T, NN, BLK, TXP>(dim3(M / TXP, sp.n2, sp.bk), dim3(TXP * G), s, d, lay, TXP, sp, t,
                                                     partials);
             else
-                zprecond_dispatch<T, NN, BLK, 0>(dim3(1, sp.n2), dim3(M * G), s, d, lay, M, sp, t, partials);
+                zprecond_dispatch<T, NN, BLK, 0>(dim3(1, sp.n2, sp.bk), dim3(M * G), s, d, lay, M, sp, t, partials);
         })
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
@@ -1341,7 +1347,7 @@ int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, v
     const int planes = yax ? lay.n3 : lay.n2;
     if (L == 1) {
         const int TX = M < 256 ? M : 256;
-        colop_dispatch<T, 1, 0>(op, dim3(M / TX, planes), dim3(TX), s, a, b, lay.ps, lay.cs, TX, sp, t);
+        colop_dispatch<T, 1, 0>(op, dim3(M / TX, planes, sp.bk), dim3(TX), s, a, b, lay.ps, lay.cs, TX, sp, t);
     } else {
         NM_SIZE_SWITCH(L, {
             constexpr int G = NN / colop_radix<T, NN>();
@@ -1350,13 +1356,13 @@ int launch_colop(int op, const SpecParams& sp, const SpecLayout& lay, void* S, v
             constexpr int TXZ = colop_block<T, NN, ZOP_STRAIN>() / G;
             if (yax ? M >= TXY : M >= TXZ) {
                 if (yax)
-                    colop_dispatch<T, NN, TXY>(op, dim3(M / TXY, planes), dim3(TXY * G), s, a, b, lay.ps, lay.cs, TXY,
-                                               sp, t);
+                    colop_dispatch<T, NN, TXY>(op, dim3(M / TXY, planes, sp.bk), dim3(TXY * G), s, a, b, lay.ps, lay.cs,
+                                               TXY, sp, t);
                 else
-                    colop_dispatch<T, NN, TXZ>(op, dim3(M / TXZ, planes), dim3(TXZ * G), s, a, b, lay.ps, lay.cs, TXZ,
-                                               sp, t);
+                    colop_dispatch<T, NN, TXZ>(op, dim3(M / TXZ, planes, sp.bk), dim3(TXZ * G), s, a, b, lay.ps, lay.cs,
+                                               TXZ, sp, t);
             } else {
-                colop_dispatch<T, NN, 0>(op, dim3(1, planes), dim3(M * G), s, a, b, lay.ps, lay.cs, M, sp, t);
+                colop_dispatch<T, NN, 0>(op, dim3(1, planes, sp.bk), dim3(M * G), s, a, b, lay.ps, lay.cs, M, sp, t);
             }
         })
     }

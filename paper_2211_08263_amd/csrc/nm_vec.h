@@ -17,6 +17,11 @@ int launch_loop_init(double* scal, double thr2, int limit, int fixed, hipStream_
 // counts the iteration and sets S_STOP when the loop is done (see ScalarSlot).
 int launch_reduce(const double* partials, int n, double* scal, int action, int slot, hipStream_t s,
                   bool guarded = false);
+// The same for nb independent Krylov loops run together (one block per loop): loop b sums
+// partials [b n, (b + 1) n) into scal + b S_COUNT.  A loop whose S_STOP is set is frozen
+// instead of skipped: RED_ALPHA and RED_BETA then store zero, so that its iterate receives the
+// deferred last update once and then stays, and RED_RR_CHECK no longer counts.
+int launch_reduce_multi(const double* partials, int n, int nb, double* scal, int action, hipStream_t s);
 
 // Number of partials written by the grid-stride kernels below.
 int vec_blocks(long n);

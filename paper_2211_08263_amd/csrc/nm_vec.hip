@@ -71,6 +71,48 @@ __global__ __launch_bounds__(1024) void k_reduce(const double* __restrict__ part
     }
 }
 
+__global__ __launch_bounds__(1024) void k_reduce_multi(const double* __restrict__ part, int n, double* scal_all,
+                                                       int action)
+{
+    const double* pb = part + (long)blockIdx.x * n;
+    double* scal = scal_all + (long)blockIdx.x * S_COUNT;
+    double v = 0.0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) v += pb[i];
+    const double s = block_sum_v(v);
+    if (threadIdx.x == 0) {
+        const bool frozen = scal[S_STOP] != 0.0;
+        switch (action) {
+        case RED_RR_CHECK: {
+            if (frozen) break;
+            scal[S_RR] = s;
+            const double it = scal[S_ITER] + 1.0;
+            scal[S_ITER] = it;
+            if (s <= scal[S_THR2] || it >= scal[S_LIMIT] || !(s < 1e300)) scal[S_STOP] = 1.0;
+            break;
+        }
+        case RED_ALPHA:
+            scal[S_PQ] = s;
+            scal[S_ALPHA] = frozen ? 0.0 : scal[S_RZ] / s;
+            break;
+        case RED_RZ_INIT:
+            scal[S_RZ] = s;
+            scal[S_FIRST] = 1.0;
+            break;
+        case RED_BETA:
+            scal[S_BETA] = frozen ? 0.0 : s / scal[S_RZ];
+            scal[S_RZ] = s;
+            scal[S_FIRST] = 0.0;
+            break;
+        default: scal[S_RR] = s; break;
+        }
+    }
+}
+int launch_reduce_multi(const double* partials, int n, int nb, double* scal, int action, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_reduce_multi, dim3(nb), dim3(1024), 0, s, partials, n, scal, action);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
 // x += alpha p with alpha read from the device
 template <typename T>
 __global__ __launch_bounds__(kBlock) void k_axpy_scal(T* __restrict__ x, const T* __restrict__ p,

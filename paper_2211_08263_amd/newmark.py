@@ -60,7 +60,8 @@ class _Options(C.Structure):
     _fields_ = [("precision", C.c_int), ("route", C.c_int), ("tol", C.c_double), ("max_iter", C.c_int),
                 ("inner_tol", C.c_double), ("max_sweeps", C.c_int), ("warm_start", C.c_int),
                 ("green_tol", C.c_double), ("compute_reaction", C.c_int), ("true_residual", C.c_int),
-                ("green_in", C.c_void_p), ("green_progress", C.c_void_p), ("green_progress_user", C.c_void_p)]
+                ("green_in", C.c_void_p), ("green_progress", C.c_void_p), ("green_progress_user", C.c_void_p),
+                ("green_batch", C.c_int)]
 
 
 GREEN_PROGRESS = C.CFUNCTYPE(None, C.c_int64, C.c_int64, C.c_void_p)
@@ -162,6 +163,7 @@ class Options:
     true_residual: int = 0
     green_in: Optional[np.ndarray] = None  # stored Green matrix to reuse (GREEN route)
     green_progress: object = None  # callable(done, total) after each unit-force solve (GREEN route)
+    green_batch: int = 0  # unit-force solves run together: 0 automatic, 1 one at a time, k >= 2 k at a time
 
 
 class Context:
@@ -240,7 +242,7 @@ def newmark_init(dim: int, n: Sequence[int], L: Sequence[float], phase_id, C_voi
         cb = GREEN_PROGRESS(lambda done, total, _u: user_cb(int(done), int(total)))
     op = _Options(o.precision, o.route, o.tol, o.max_iter, o.inner_tol, o.max_sweeps, o.warm_start, o.green_tol,
                   o.compute_reaction, o.true_residual, None if gin is None else gin.ctypes.data,
-                  None if cb is None else C.cast(cb, C.c_void_p).value, None)
+                  None if cb is None else C.cast(cb, C.c_void_p).value, None, int(o.green_batch))
     out = C.c_void_p()
     code = lib.nm_newmark_init(C.byref(pb), C.byref(op), stream, C.byref(out))
     ctx = Context(out.value, (ph, Cv, rh, g, dm), int(dim), tuple(nn), int(g.size))

@@ -101,3 +101,37 @@ def test_mixed_precision_green_route():
     # the FP64 residual of the u_b solve (zero at the first step, whose right-hand side is zero)
     assert all(x["relres"] <= 1e-10 and x["relres0"] >= x["relres"] for x in st)
     assert all(x["relres"] > 0 for x in st[1:])
+
+
+@pytest.mark.parametrize("case", ["polycrystal-16-sphere", "disc2d", "spheres-32-slab"])
+def test_unit_force_solves_run_together(case):
+    """Several unit-force solves through one chain of kernels (fields side by side, each loop
+    with its own scalars, frozen once converged) give the Green matrix the one-at-a-time solves
+    give (FP64), and the same trajectory."""
+    import time
+    if case == "disc2d":
+        pb = W.make_disc2d()
+    elif case == "spheres-32-slab":
+        pb = W.make_spheres3d(n=32, seed=2)
+    else:
+        pb = W.make_polycrystal(n=16, n_grains=6, seed=7, gamma="sphere", sphere_radius=1.5)
+    nd = pb.dim * pb.gamma_idx.size
+    res = {}
+    for batch in (1, 0, 5):
+        opts = nmb.Options(tol=1e-10, max_iter=800, route=nmb.ROUTE_GREEN, green_tol=1e-12, green_batch=batch)
+        t0 = time.perf_counter()
+        with nmb.newmark_init_problem(pb, opts) as ctx:
+            t_init = time.perf_counter() - t0
+            G = nmb.green_matrix(ctx)
+            for s in range(4):
+                nmb.newmark_step(ctx, pb.U(s + 1))
+            u = nmb.get_state(ctx)["u"].copy()
+        res[batch] = (G, u, t_init)
+    G1, u1, t1 = res[1]
+    for batch in (0, 5):
+        G, u, t = res[batch]
+        eg = float(np.abs(G - G1).max() / np.abs(G1).max())
+        eu = float(np.abs(u - u1).max() / np.abs(u1).max())
+        print(f"{case}: {nd} unit-force solves, one at a time {t1:.2f} s, batch {batch or 'auto'} {t:.2f} s; "
+              f"G max rel diff {eg:.1e}, u {eu:.1e}", flush=True)
+        assert eg <= 1e-13 and eu <= 1e-12
