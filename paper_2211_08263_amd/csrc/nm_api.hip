@@ -640,13 +640,17 @@ int green_solve(nm_ctx* c, const double* rhs, double* x, double bref, double tol
 
 // Fields solved together by the Green route's unit-force solves: enough to give the kernels
 // about 8M voxels of work (small grids are bound by launches, not by memory traffic), at most
-// 16; options.green_batch overrides (1: one at a time).  0 when the launch layout does not
-// keep every field's partial sums apart.
+// 16; options.green_batch overrides (1: one at a time).  The fields solved together run in
+// FP64, so a mixed-precision context keeps its one-at-a-time FP32 solves above 2^18 voxels,
+// where those are no longer launch-bound and move half the bytes (measured at 64^3: 4.0 ms per
+// mixed solve one at a time, 1.65 ms per FP64 solve sixteen at a time).  1 when the launch
+// layout does not keep every field's partial sums apart.
 int green_batch_size(nm_ctx* c)
 {
     int nb = c->opt.green_batch;
     if (nb <= 0) {
         nb = 1;
+        if (c->opt.precision == NM_PREC_MIXED && c->N > (1L << 18)) return 1;
         while (nb < 16 && (long)nb * 2 * c->N <= (8L << 20)) nb *= 2;
     }
     if (nb > 64) nb = 64;
