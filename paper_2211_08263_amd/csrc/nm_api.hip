@@ -84,6 +84,9 @@ struct nm_ctx {
     std::vector<double> G, F_last; // G: host copy (row major) for nm_green_matrix
     double* Gdev = nullptr;        // G, then its LU factors (column major, d n_gamma square)
     int* pivdev = nullptr;         // row swaps of the factorization
+    int* permdev = nullptr;        // the swaps composed into one row permutation
+    double* dinvdev = nullptr;     // inverted diagonal blocks of the factors (per 64-column panel)
+    double* luwork = nullptr;      // 2 x (d n_gamma) work vector of the substitutions
     int* singdev = nullptr;        // set by the factorization on a zero pivot
     int green_sweeps = 0, green_inner = 0; // mixed-precision Green route: running totals
     // several unit-force solves at once (Green route preprocessing): fields [b][3][N] and
@@ -784,6 +787,9 @@ int build_green(nm_ctx* c, const double* G_in)
     const long nd = (long)d * c->ng;
     CHK(dalloc(c, &c->Gdev, (size_t)nd * nd));
     CHK(dalloc(c, &c->pivdev, nd));
+    CHK(dalloc(c, &c->permdev, nd));
+    CHK(dalloc(c, &c->dinvdev, (size_t)((nd + 63) / 64) * 2 * 64 * 64));
+    CHK(dalloc(c, &c->luwork, 2 * (size_t)nd));
     CHK(dalloc(c, &c->singdev, 1));
     c->G.assign((size_t)nd * nd, 0.0);
     if (G_in) {
@@ -873,6 +879,8 @@ int build_green(nm_ctx* c, const double* G_in)
     HIPCHK(c, hipMemcpyAsync(&sing, c->singdev, sizeof(int), hipMemcpyDeviceToHost, s));
     HIPCHK(c, hipStreamSynchronize(s));
     if (sing) return fail(c, NM_ESINGULAR, "zero pivot in the Green matrix");
+    LCHK(c, lu_prepare_solve(c->Gdev, (int)nd, c->pivdev, c->permdev, c->dinvdev, s));
+    HIPCHK(c, hipStreamSynchronize(s));
     return NM_OK;
 }
 
@@ -1367,7 +1375,7 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         // the device: Fdev holds V, then F (d per point), gbuf the force with 3 components
         LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));
         LCHK(c, launch_green_rhs(c->Fdev, c->gbuf, c->Ubuf, per_point, c->ng, d, s));
-        LCHK(c, lu_solve_device(c->Gdev, nd, c->pivdev, c->Fdev, s));
+        LCHK(c, lu_solve_device(c->Gdev, nd, c->permdev, c->dinvdev, c->Fdev, c->luwork, s));
         LCHK(c, launch_green_force(c->gbuf, c->Fdev, 1.0 / c->sp.bdt2, c->ng, d, s));
         // f = F on Gamma (reuse b, no longer needed) ; A u_f = f from the previous u_f
         LCHK(c, launch_fill<double>(c->b, 0.0, n, s));
@@ -1821,7 +1829,7 @@ int nm_green_solve(nm_ctx* c, const double* V, double* X)
     double* buf = nullptr;
     CHK(dalloc(c, &buf, nd));
     HIPCHK(c, hipMemcpyAsync(buf, V, nd * sizeof(double), hipMemcpyHostToDevice, c->stream));
-    LCHK(c, lu_solve_device(c->Gdev, (int)nd, c->pivdev, buf, c->stream));
+    LCHK(c, lu_solve_device(c->Gdev, (int)nd, c->permdev, c->dinvdev, buf, c->luwork, c->stream));
     HIPCHK(c, hipMemcpyAsync(X, buf, nd * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c->allocs.erase(std::find(c->allocs.begin(), c->allocs.end(), (void*)buf));

@@ -9,8 +9,13 @@ namespace nm {
 // (unit lower L below the diagonal, U on and above it); piv[j] is the row swapped with
 // row j at step j.  *sing (device) is set to 1 when a pivot is zero.  Asynchronous.
 int lu_factor_device(double* A, int n, int* piv, int* sing, hipStream_t s);
-// b <- A^-1 b with the factors of lu_factor_device.  Asynchronous.
-int lu_solve_device(const double* LU, int n, const int* piv, double* b, hipStream_t s);
+// After lu_factor_device: the pivots composed into one row permutation (perm, n ints) and the
+// inverses of the diagonal blocks of every panel (dinv, 2 * 64 * 64 doubles per 64 columns), so
+// that a solve is one gather and one launch per panel and direction.  Asynchronous.
+int lu_prepare_solve(const double* LU, int n, const int* piv, int* perm, double* dinv, hipStream_t s);
+// b <- A^-1 b with those factors; work: 2 n doubles.  Asynchronous.
+int lu_solve_device(const double* LU, int n, const int* perm, const double* dinv, double* b, double* work,
+                    hipStream_t s);
 // Column dst of the column-major G (leading dimension nd) from a Gamma trace g (3 values
 // per point): G[d q + i][dst] = g[3 q + i].
 int launch_green_column(double* G, long nd, long dst, const double* g, long ng, int d, hipStream_t s);

@@ -183,72 +183,117 @@ int lu_factor_device(double* A, int n, int* piv, int* sing, hipStream_t s)
     return 0;
 }
 
-// Row swaps of the factorization applied to b (in order).  One thread.
-__global__ void k_lu_perm(double* __restrict__ b, int n, const int* __restrict__ piv)
+// The row swaps of the factorization composed into one permutation (one thread, once per
+// factorization): after the swaps, row i of b holds the original row perm[i].
+__global__ void k_lu_perm_from_piv(const int* __restrict__ piv, int* __restrict__ perm, int n)
 {
     if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    for (int i = 0; i < n; i++) perm[i] = i;
     for (int j = 0; j < n; j++) {
         const int p = piv[j];
         if (p != j) {
-            const double t = b[j];
-            b[j] = b[p];
-            b[p] = t;
+            const int t = perm[j];
+            perm[j] = perm[p];
+            perm[p] = t;
         }
     }
 }
 
-// Solve the triangle of rows/columns [k0, k1) in place (one block of kNb threads): unit
-// lower (LOWER) or upper.
-template <bool LOWER> __global__ __launch_bounds__(kNb) void k_tri_block(const double* __restrict__ A, int n,
-                                                                           double* __restrict__ b, int k0, int k1)
+// Inverses of the diagonal blocks of one panel (block per panel, kNb threads; thread j
+// forms column j): dinv[0 .. kNb^2) = L_kk^-1 (unit lower), dinv[kNb^2 .. 2 kNb^2) = U_kk^-1,
+// row major, zero outside the triangle.
+__global__ __launch_bounds__(kNb) void k_lu_diag_inv(const double* __restrict__ A, int n, double* __restrict__ dinv)
 {
-    __shared__ double x[kNb];
+    const int k0 = blockIdx.x * kNb;
+    const int kb = n - k0 < kNb ? n - k0 : kNb;
+    const int j = threadIdx.x;
+    double* Li = dinv + (long)blockIdx.x * 2 * kNb * kNb;
+    double* Ui = Li + kNb * kNb;
+    for (int i = 0; i < kNb; i++) {
+        Li[i * kNb + j] = 0.0;
+        Ui[i * kNb + j] = 0.0;
+    }
+    if (j >= kb) return;
+    // L x = e_j: x_i = -sum_{j <= q < i} L_iq x_q below the unit diagonal
+    double x[kNb];
+    for (int i = 0; i < kNb; i++) x[i] = 0.0;
+    x[j] = 1.0;
+    for (int i = j + 1; i < kb; i++) {
+        double acc = 0.0;
+        for (int q = j; q < i; q++) acc += A[(long)(k0 + q) * n + (k0 + i)] * x[q];
+        x[i] = -acc;
+    }
+    for (int i = j; i < kb; i++) Li[i * kNb + j] = x[i];
+    // U x = e_j: x_j = 1 / U_jj, x_i = -(sum_{i < q <= j} U_iq x_q) / U_ii above it
+    for (int i = 0; i < kNb; i++) x[i] = 0.0;
+    x[j] = 1.0 / A[(long)(k0 + j) * n + (k0 + j)];
+    for (int i = j - 1; i >= 0; i--) {
+        double acc = 0.0;
+        for (int q = i + 1; q <= j; q++) acc += A[(long)(k0 + q) * n + (k0 + i)] * x[q];
+        x[i] = -acc / A[(long)(k0 + i) * n + (k0 + i)];
+    }
+    for (int i = 0; i <= j; i++) Ui[i * kNb + j] = x[i];
+}
+
+int lu_prepare_solve(const double* LU, int n, const int* piv, int* perm, double* dinv, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_lu_perm_from_piv, dim3(1), dim3(1), 0, s, piv, perm, n);
+    const int np = (n + kNb - 1) / kNb;
+    hipLaunchKernelGGL(k_lu_diag_inv, dim3(np), dim3(kNb), 0, s, LU, n, dinv);
+    return hipGetLastError() == hipSuccess ? 0 : -2;
+}
+
+__global__ __launch_bounds__(256) void k_lu_gather(const double* __restrict__ b, const int* __restrict__ perm,
+                                                   double* __restrict__ w, int n)
+{
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) w[i] = b[perm[i]];
+}
+
+// One panel of a substitution: x_k = D_k in[k0:k1] with D_k the inverted diagonal block
+// (every block forms it; block 0 stores it in out[k0:k1]), then in[r] -= A[r, k0:k1] x_k for
+// the rows r in [r0, r1) (one thread per row).  Those rows lie outside [k0, k1), so no block
+// reads an entry another block writes.
+__global__ __launch_bounds__(256) void k_tri_panel(const double* __restrict__ A, int n, const double* __restrict__ D,
+                                                   double* __restrict__ in, double* __restrict__ out, int k0, int k1,
+                                                   int r0, int r1)
+{
+    __shared__ double xs[kNb];
     const int t = threadIdx.x;
     const int kb = k1 - k0;
-    if (t < kb) x[t] = b[k0 + t];
+    if (t < kNb) {
+        double acc = 0.0;
+        if (t < kb)
+            for (int q = 0; q < kb; q++) acc += D[t * kNb + q] * in[k0 + q];
+        xs[t] = acc;
+    }
     __syncthreads();
-    if (LOWER) {
-        for (int q = 0; q < kb; q++) {
-            // column q of L below the diagonal
-            if (t > q && t < kb) x[t] -= A[(long)(k0 + q) * n + (k0 + t)] * x[q];
-            __syncthreads();
-        }
-    } else {
-        for (int q = kb - 1; q >= 0; q--) {
-            if (t == q) x[q] /= A[(long)(k0 + q) * n + (k0 + q)];
-            __syncthreads();
-            if (t < q) x[t] -= A[(long)(k0 + q) * n + (k0 + t)] * x[q];
-            __syncthreads();
-        }
+    if (blockIdx.x == 0 && t < kb) out[k0 + t] = xs[t];
+    const int r = r0 + blockIdx.x * blockDim.x + t;
+    if (r < r1) {
+        double acc = 0.0;
+        for (int q = 0; q < kb; q++) acc += A[(long)(k0 + q) * n + r] * xs[q];
+        in[r] -= acc;
     }
-    if (t < kb) b[k0 + t] = x[t];
 }
 
-// b[rows] -= A[rows, k0:k1] x[k0:k1] for rows in [r0, r1) (one thread per row).
-__global__ __launch_bounds__(256) void k_tri_update(const double* __restrict__ A, int n, double* __restrict__ b,
-                                                    int k0, int k1, int r0, int r1)
+int lu_solve_device(const double* LU, int n, const int* perm, const double* dinv, double* b, double* work,
+                    hipStream_t s)
 {
-    const int r = r0 + blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= r1) return;
-    double s = 0.0;
-    for (int q = k0; q < k1; q++) s += A[(long)q * n + r] * b[q];
-    b[r] -= s;
-}
-
-int lu_solve_device(const double* LU, int n, const int* piv, double* b, hipStream_t s)
-{
-    hipLaunchKernelGGL(k_lu_perm, dim3(1), dim3(1), 0, s, b, n, piv);
-    for (int k0 = 0; k0 < n; k0 += kNb) {
-        const int k1 = k0 + kNb < n ? k0 + kNb : n;
-        hipLaunchKernelGGL((k_tri_block<true>), dim3(1), dim3(kNb), 0, s, LU, n, b, k0, k1);
-        if (k1 < n)
-            hipLaunchKernelGGL(k_tri_update, dim3((n - k1 + 255) / 256), dim3(256), 0, s, LU, n, b, k0, k1, k1, n);
+    double* w = work;      // P b, then the forward residuals
+    double* y = work + n;  // L^-1 P b, then the backward residuals
+    hipLaunchKernelGGL(k_lu_gather, dim3((n + 255) / 256), dim3(256), 0, s, b, perm, w, n);
+    const int np = (n + kNb - 1) / kNb;
+    for (int k = 0; k < np; k++) {
+        const int k0 = k * kNb, k1 = k0 + kNb < n ? k0 + kNb : n;
+        const int rows = n - k1;
+        hipLaunchKernelGGL(k_tri_panel, dim3(rows > 0 ? (rows + 255) / 256 : 1), dim3(256), 0, s, LU, n,
+                           dinv + (long)k * 2 * kNb * kNb, w, y, k0, k1, k1, n);
     }
-    for (int k1 = n; k1 > 0; k1 -= (k1 % kNb ? k1 % kNb : kNb)) {
-        const int k0 = ((k1 - 1) / kNb) * kNb;
-        hipLaunchKernelGGL((k_tri_block<false>), dim3(1), dim3(kNb), 0, s, LU, n, b, k0, k1);
-        if (k0 > 0)
-            hipLaunchKernelGGL(k_tri_update, dim3((k0 + 255) / 256), dim3(256), 0, s, LU, n, b, k0, k1, 0, k0);
+    for (int k = np - 1; k >= 0; k--) {
+        const int k0 = k * kNb, k1 = k0 + kNb < n ? k0 + kNb : n;
+        hipLaunchKernelGGL(k_tri_panel, dim3(k0 > 0 ? (k0 + 255) / 256 : 1), dim3(256), 0, s, LU, n,
+                           dinv + (long)k * 2 * kNb * kNb + kNb * kNb, y, b, k0, k1, 0, k0);
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
