@@ -111,11 +111,11 @@ typedef struct nm_options {
                                  unit-force solve of nm_newmark_init, or each group solved together
                                  (may be NULL) */
     void* green_progress_user;
-    int green_batch;          /* GREEN route: unit-force solves run together through one chain of kernels
-                                 (FP64, each giving the column a single solve gives): 0 picks the number
-                                 from the grid (about 8M voxels of work, at most 16; in mixed precision
-                                 only up to 2^18 voxels), 1 solves one at a time in the context's
-                                 precision, k >= 2 solves k at a time (at most 64) */
+    int green_batch;          /* GREEN route: unit-force solves run together through one chain of kernels,
+                                 in the context's precision (FP64: each column bit for bit the one a
+                                 single solve gives): 0 picks the number from the grid (about 8M voxels of
+                                 work, at most 16), 1 solves one at a time, k >= 2 solves k at a time (at
+                                 most 64) */
 } nm_options;
 
 typedef struct nm_step_stats {

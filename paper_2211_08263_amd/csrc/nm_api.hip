@@ -92,8 +92,10 @@ struct nm_ctx {
     // several unit-force solves at once (Green route preprocessing): fields [b][3][N] and
     // spectra [b][6 cs] of up to mnb solves, their partial sums and scalar blocks
     int mnb = 0;
-    double *mX = nullptr, *mR = nullptr, *mP = nullptr, *mQ = nullptr, *mU = nullptr;
+    double *mX = nullptr, *mR = nullptr, *mP = nullptr, *mQ = nullptr, *mU = nullptr, *mB = nullptr;
     double2 *mS = nullptr, *mS2 = nullptr;
+    float *mD32 = nullptr, *mR32 = nullptr, *mP32 = nullptr, *mQ32 = nullptr; // mixed precision
+    float2 *mS32 = nullptr, *mS2_32 = nullptr;
     double *mpa = nullptr, *mpb = nullptr, *mscal = nullptr, *mhscal = nullptr;
     // explicit central-difference scheme (beta == 0)
     bool explicit_scheme = false;
@@ -643,17 +645,13 @@ int green_solve(nm_ctx* c, const double* rhs, double* x, double bref, double tol
 
 // Fields solved together by the Green route's unit-force solves: enough to give the kernels
 // about 8M voxels of work (small grids are bound by launches, not by memory traffic), at most
-// 16; options.green_batch overrides (1: one at a time).  The fields solved together run in
-// FP64, so a mixed-precision context keeps its one-at-a-time FP32 solves above 2^18 voxels,
-// where those are no longer launch-bound and move half the bytes (measured at 64^3: 4.0 ms per
-// mixed solve one at a time, 1.65 ms per FP64 solve sixteen at a time).  1 when the launch
-// layout does not keep every field's partial sums apart.
+// 16; options.green_batch overrides (1: one at a time).  1 when the launch layout does not keep
+// every field's partial sums apart.
 int green_batch_size(nm_ctx* c)
 {
     int nb = c->opt.green_batch;
     if (nb <= 0) {
         nb = 1;
-        if (c->opt.precision == NM_PREC_MIXED && c->N > (1L << 18)) return 1;
         while (nb < 16 && (long)nb * 2 * c->N <= (8L << 20)) nb *= 2;
     }
     if (nb > 64) nb = 64;
@@ -664,91 +662,118 @@ int green_batch_size(nm_ctx* c)
     return nb;
 }
 
-// nb independent unmasked FP64 solves A x_b = r_b from x_b = 0 through one chain of kernels:
-// c->mR holds the right-hand sides on entry (then the residuals), c->mX receives the
-// solutions; each loop stops on ||r_b|| <= tol ||rhs_b|| and is frozen from then on (the
-// multi-loop reductions), so that every solution is the one a single solve gives.
-int pcg_multi(nm_ctx* c, int nb, double tol, int* iters_max)
+// Buffers of nb fields side by side in one precision: real fields [b][3][N], spectra
+// [b][6 cs], per-field device scalars.
+template <typename T> struct MultiBufs {
+    T *x, *r, *p, *q;
+    cx_t<T>*S, *S2;
+};
+
+// Launch layout of nb fields side by side (3-component passes, the 6-component stress pass,
+// the column passes).
+struct MultiLayout {
+    SpecLayout lay3, lay6;
+    SpecParams sp;
+    long lpf;
+};
+MultiLayout multi_layout(nm_ctx* c, int nb)
+{
+    MultiLayout m;
+    m.lpf = 3L * c->n2 * c->n3;
+    m.lay3 = c->lay;
+    m.lay3.stop = nullptr;
+    m.lay3.nb = nb;
+    m.lay3.bc = 3;
+    m.lay3.bs = 6 * c->lay.cs;
+    m.lay6 = m.lay3;
+    m.lay6.bc = 1;
+    m.sp = c->sp;
+    m.sp.stop = nullptr;
+    m.sp.bs = 6 * c->lay.cs;
+    m.sp.bk = nb;
+    return m;
+}
+
+// The six passes of q = A p after the x-forward one, for nb fields (S holds their x spectra).
+// partials (or null): per-block sums of p.q, field after field.
+template <typename T>
+int multi_operator_rest(nm_ctx* c, const MultiLayout& L, int nb, const MultiBufs<T>& m, const T* p, T* q,
+                        double* partials)
+{
+    hipStream_t s = c->stream;
+    const void* tw = Prec<T>::tw(c);
+    LCHK(c, launch_colop<T>(YOP_DERIV, L.sp, L.lay3, m.S, m.S2, tw, s));
+    LCHK(c, launch_colop<T>(ZOP_STRAIN, L.sp, L.lay3, m.S, m.S2, tw, s));
+    LCHK(c, launch_xstress<T>(c->n1, m.S2, L.lay6, c->phase, Prec<T>::C(c), tw, s));
+    LCHK(c, launch_colop<T>(YOP_DIV, L.sp, L.lay3, m.S, m.S2, tw, s));
+    LCHK(c, launch_colop<T>(ZOP_DIVZ, L.sp, L.lay3, m.S, m.S2, tw, s));
+    XInvArgs ia = xi_args(c, m.S, q, p, Prec<T>::rho(c), nullptr, partials);
+    ia.lay = L.lay3;
+    ia.nlines = nb * L.lpf;
+    ia.lines_per_batch = L.lpf;
+    LCHK(c, launch_xinv<T>(XI_OPERATOR, c->n1, ia, tw, s));
+    return NM_OK;
+}
+
+// nb independent unmasked PCG loops in precision T through one chain of kernels, from x_b = 0
+// with the residuals already in m.r: loop b stops on r.r <= thr2[b] (or max_iter) and is
+// frozen from then on (the multi-loop reductions: alpha = beta = 0), so that its iterate
+// receives the deferred last update once and then stays; loops with frozen[b] start stopped.
+// On return every x_b still lacks its deferred last alpha p (alpha is zero for the loops
+// frozen before the last iteration); c->mhscal holds the final scalars.
+template <typename T>
+int pcg_multi_core(nm_ctx* c, int nb, const MultiBufs<T>& m, const double* rr, const double* thr2,
+                   const bool* frozen, int max_iter, int* iters_max)
 {
     hipStream_t s = c->stream;
     const long n = 3 * c->N;
-    const long lpf = 3L * c->n2 * c->n3;
-    const long bs = 6 * c->lay.cs;
-    SpecLayout lay3 = c->lay;
-    lay3.stop = nullptr;
-    lay3.nb = nb;
-    lay3.bc = 3;
-    lay3.bs = bs;
-    SpecLayout lay6 = lay3;
-    lay6.bc = 1;
-    SpecParams sp = c->sp;
-    sp.stop = nullptr;
-    sp.bs = bs;
-    sp.bk = nb;
-    const int nbx = xinv_blocks(c->n1, lpf), nbf = xfwd_blocks(c->n1, lpf), nbz = zprecond_blocks<double>(c->sp);
-    const double2* tw = c->tw64;
-    // r.r of each right-hand side (the zero start's residual) and the loop thresholds
-    std::vector<double> thr2(nb);
+    const MultiLayout L = multi_layout(c, nb);
+    const int nbx = xinv_blocks(c->n1, L.lpf), nbf = xfwd_blocks(c->n1, L.lpf), nbz = zprecond_blocks<T>(c->sp);
+    const void* tw = Prec<T>::tw(c);
     for (int b = 0; b < nb; b++) {
-        LCHK(c, launch_dot<double>(c->mR + b * n, c->mR + b * n, n, c->part_a, s));
-        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->mscal + b * S_COUNT, RED_STORE_RR, 0, s));
+        LCHK(c, launch_loop_init(c->mscal + b * S_COUNT, thr2[b], max_iter, 0, s));
+        if (frozen[b]) LCHK(c, launch_fill<double>(c->mscal + b * S_COUNT + S_STOP, 1.0, 1, s));
+        (void)rr;
     }
-    HIPCHK(c, hipMemcpyAsync(c->mhscal, c->mscal, nb * S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
-    HIPCHK(c, hipStreamSynchronize(s));
-    for (int b = 0; b < nb; b++) {
-        const double rr = c->mhscal[b * S_COUNT + S_RR];
-        if (!(rr > 0) || !std::isfinite(rr)) return fail(c, NM_EINVAL, "unit-force right-hand side %d is zero", b);
-        thr2[b] = tol * tol * rr;
-        LCHK(c, launch_loop_init(c->mscal + b * S_COUNT, thr2[b], c->opt.max_iter, 0, s));
-    }
-    LCHK(c, launch_fill<double>(c->mX, 0.0, nb * n, s));
+    LCHK(c, launch_fill<T>(m.x, (T)0, nb * n, s));
     // z = M r as its x spectrum, r.z
     XFwdArgs fa{};
-    fa.spec = c->mS;
-    fa.lay = lay3;
+    fa.spec = m.S;
+    fa.lay = L.lay3;
     fa.scal = c->mscal;
-    fa.nlines = nb * lpf;
-    fa.lines_per_batch = lpf;
-    fa.src = c->mR;
-    LCHK(c, launch_xfwd<double>(XF_PLAIN, c->n1, fa, tw, s));
-    LCHK(c, launch_ypass<double>(-1, 3 * nb, lay3, c->mS, tw, s));
-    LCHK(c, launch_zprecond<double>(sp, lay3, c->mS, tw, s, c->mpb));
-    LCHK(c, launch_ypass<double>(+1, 3 * nb, lay3, c->mS, tw, s));
+    fa.nlines = nb * L.lpf;
+    fa.lines_per_batch = L.lpf;
+    fa.src = m.r;
+    LCHK(c, launch_xfwd<T>(XF_PLAIN, c->n1, fa, tw, s));
+    LCHK(c, launch_ypass<T>(-1, 3 * nb, L.lay3, m.S, tw, s));
+    LCHK(c, launch_zprecond<T>(L.sp, L.lay3, m.S, tw, s, c->mpb));
+    LCHK(c, launch_ypass<T>(+1, 3 * nb, L.lay3, m.S, tw, s));
     LCHK(c, launch_reduce_multi(c->mpb, nbz, nb, c->mscal, RED_RZ_INIT, s));
-    XInvArgs pa = xi_args(c, c->mS, nullptr, nullptr, nullptr, nullptr, nullptr);
-    pa.lay = lay3;
-    pa.nlines = nb * lpf;
-    pa.lines_per_batch = lpf;
-    pa.p = c->mP;
-    pa.x = c->mX;
+    XInvArgs pa = xi_args(c, m.S, nullptr, nullptr, nullptr, nullptr, nullptr);
+    pa.lay = L.lay3;
+    pa.nlines = nb * L.lpf;
+    pa.lines_per_batch = L.lpf;
+    pa.p = m.p;
+    pa.x = m.x;
     pa.scal = c->mscal;
-    XInvArgs ia = xi_args(c, c->mS, c->mQ, c->mP, c->rho64, nullptr, c->mpb);
-    ia.lay = lay3;
-    ia.nlines = nb * lpf;
-    ia.lines_per_batch = lpf;
     XFwdArgs fu = fa;
     fu.src = nullptr;
-    fu.r = c->mR;
-    fu.q = c->mQ;
+    fu.r = m.r;
+    fu.q = m.q;
     fu.partials = c->mpa;
     int it = 0;
     for (;;) {
         for (int k = 0; k < 4; k++) {
             // p = z + beta p (x += alpha p_old); q = A p; alpha
-            LCHK(c, launch_xpupdate<double>(c->n1, pa, tw, s));
-            LCHK(c, launch_colop<double>(YOP_DERIV, sp, lay3, c->mS, c->mS2, tw, s));
-            LCHK(c, launch_colop<double>(ZOP_STRAIN, sp, lay3, c->mS, c->mS2, tw, s));
-            LCHK(c, launch_xstress<double>(c->n1, c->mS2, lay6, c->phase, c->C64, tw, s));
-            LCHK(c, launch_colop<double>(YOP_DIV, sp, lay3, c->mS, c->mS2, tw, s));
-            LCHK(c, launch_colop<double>(ZOP_DIVZ, sp, lay3, c->mS, c->mS2, tw, s));
-            LCHK(c, launch_xinv<double>(XI_OPERATOR, c->n1, ia, tw, s));
+            LCHK(c, launch_xpupdate<T>(c->n1, pa, tw, s));
+            CHK(multi_operator_rest<T>(c, L, nb, m, m.p, m.q, c->mpb));
             LCHK(c, launch_reduce_multi(c->mpb, nbx, nb, c->mscal, RED_ALPHA, s));
             // r -= alpha q, r.r (stop test); z = M r, r.z; beta
-            LCHK(c, launch_xfwd<double>(XF_UPDATE, c->n1, fu, tw, s));
+            LCHK(c, launch_xfwd<T>(XF_UPDATE, c->n1, fu, tw, s));
             LCHK(c, launch_reduce_multi(c->mpa, nbf, nb, c->mscal, RED_RR_CHECK, s));
-            LCHK(c, launch_ypass<double>(-1, 3 * nb, lay3, c->mS, tw, s));
-            LCHK(c, launch_zprecond<double>(sp, lay3, c->mS, tw, s, c->mpb));
-            LCHK(c, launch_ypass<double>(+1, 3 * nb, lay3, c->mS, tw, s));
+            LCHK(c, launch_ypass<T>(-1, 3 * nb, L.lay3, m.S, tw, s));
+            LCHK(c, launch_zprecond<T>(L.sp, L.lay3, m.S, tw, s, c->mpb));
+            LCHK(c, launch_ypass<T>(+1, 3 * nb, L.lay3, m.S, tw, s));
             LCHK(c, launch_reduce_multi(c->mpb, nbz, nb, c->mscal, RED_BETA, s));
         }
         HIPCHK(c, hipMemcpyAsync(c->mhscal, c->mscal, nb * S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -763,15 +788,93 @@ int pcg_multi(nm_ctx* c, int nb, double tol, int* iters_max)
         }
         if (all) break;
     }
-    // the deferred last x += alpha p (alpha is zero for the loops frozen before the last
-    // iteration, which received it already)
+    if (iters_max) *iters_max = std::max(*iters_max, it);
+    return NM_OK;
+}
+
+// nb independent unmasked solves A x_b = rhs_b from x_b = 0 (the Green route's unit-force
+// solves), c->mB holding the right-hand sides, c->mX receiving the solutions, each to
+// ||rhs_b - A x_b|| <= tol ||rhs_b||:
+//   FP64: one PCG loop per field; every solution is the one a single FP64 solve gives;
+//   mixed: FP64 iterative refinement of FP32 PCG corrections as in the single mixed solve
+//   (residual in FP64, correction to max(inner_tol, half the remaining factor), x += d),
+//   fields whose FP64 residual has converged frozen in the later corrections.
+int solve_multi(nm_ctx* c, int nb, double tol, int* iters_max)
+{
+    hipStream_t s = c->stream;
+    const long n = 3 * c->N;
+    std::vector<double> rr(nb), bref(nb), thr2(nb);
+    std::vector<char> fz(nb, 0);
+    MultiBufs<double> m64{c->mX, c->mR, c->mP, c->mQ, (cx_t<double>*)c->mS, (cx_t<double>*)c->mS2};
+    auto residuals = [&](bool x_zero) -> int {
+        // R = rhs - A X (FP64; the zero start's residual is rhs itself), its FP32 copy, r.r
+        if (!x_zero) {
+            const MultiLayout L = multi_layout(c, nb);
+            XFwdArgs fa{};
+            fa.spec = m64.S;
+            fa.lay = L.lay3;
+            fa.scal = c->mscal;
+            fa.nlines = nb * L.lpf;
+            fa.lines_per_batch = L.lpf;
+            fa.src = c->mX;
+            LCHK(c, launch_xfwd<double>(XF_PLAIN, c->n1, fa, c->tw64, s));
+            CHK(multi_operator_rest<double>(c, L, nb, m64, c->mX, c->mQ, nullptr));
+        } else {
+            LCHK(c, launch_fill<double>(c->mQ, 0.0, nb * n, s));
+        }
+        for (int b = 0; b < nb; b++) {
+            LCHK(c, launch_residual<double>(c->mB + b * n, c->mQ + b * n, c->mR + b * n, nullptr, c->N, 3, c->part_a,
+                                            s, c->mR32 ? c->mR32 + b * n : nullptr));
+            LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->mscal + b * S_COUNT, RED_STORE_RR, 0, s));
+        }
+        HIPCHK(c, hipMemcpyAsync(c->mhscal, c->mscal, nb * S_COUNT * sizeof(double), hipMemcpyDeviceToHost, s));
+        HIPCHK(c, hipStreamSynchronize(s));
+        for (int b = 0; b < nb; b++) {
+            rr[b] = c->mhscal[b * S_COUNT + S_RR];
+            if (!std::isfinite(rr[b])) return fail(c, NM_ENAN, "non-finite residual in unit-force solve %d", b);
+        }
+        return NM_OK;
+    };
+    CHK(residuals(true));
     for (int b = 0; b < nb; b++) {
-        if (!(c->mhscal[b * S_COUNT + S_RR] <= thr2[b]))
-            return fail(c, NM_ENOTCONV, "unit-force solve did not reach tol %.3g in %d iterations", tol,
-                        (int)c->mhscal[b * S_COUNT + S_ITER]);
-        LCHK(c, launch_axpy_scal<double>(c->mX + b * n, c->mP + b * n, c->mscal + b * S_COUNT + S_ALPHA, n, s));
+        if (!(rr[b] > 0)) return fail(c, NM_EINVAL, "unit-force right-hand side %d is zero", b);
+        bref[b] = std::sqrt(rr[b]);
     }
-    if (iters_max) *iters_max = it;
+    if (c->opt.precision != NM_PREC_MIXED) {
+        for (int b = 0; b < nb; b++) thr2[b] = tol * tol * rr[b];
+        const bool none[64] = {};
+        CHK(pcg_multi_core<double>(c, nb, m64, rr.data(), thr2.data(), none, c->opt.max_iter, iters_max));
+        // the deferred last x += alpha p (zero for the loops frozen before the last iteration)
+        for (int b = 0; b < nb; b++) {
+            if (!(c->mhscal[b * S_COUNT + S_RR] <= thr2[b]))
+                return fail(c, NM_ENOTCONV, "unit-force solve did not reach tol %.3g in %d iterations", tol,
+                            (int)c->mhscal[b * S_COUNT + S_ITER]);
+            LCHK(c, launch_axpy_scal<double>(c->mX + b * n, c->mP + b * n, c->mscal + b * S_COUNT + S_ALPHA, n, s));
+        }
+        return NM_OK;
+    }
+    MultiBufs<float> m32{c->mD32, c->mR32, c->mP32, c->mQ32, (cx_t<float>*)c->mS32, (cx_t<float>*)c->mS2_32};
+    LCHK(c, launch_fill<double>(c->mX, 0.0, nb * n, s));
+    for (int sweep = 0;; sweep++) {
+        if (sweep > 0) CHK(residuals(false));
+        bool all = true;
+        bool frozen[64];
+        for (int b = 0; b < nb; b++) {
+            frozen[b] = std::sqrt(rr[b]) <= tol * bref[b];
+            all = all && frozen[b];
+            const double need = 0.5 * tol * bref[b] / std::sqrt(rr[b]);
+            const double t = need > c->opt.inner_tol ? need : c->opt.inner_tol;
+            thr2[b] = t * t * rr[b];
+        }
+        if (all) break;
+        if (sweep >= c->opt.max_sweeps)
+            return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps", tol, sweep);
+        CHK(pcg_multi_core<float>(c, nb, m32, rr.data(), thr2.data(), frozen, c->opt.max_iter, iters_max));
+        // X += D + alpha P (the correction's deferred last update folded in FP64)
+        for (int b = 0; b < nb; b++)
+            LCHK(c, launch_add_f2d_axpy(c->mX + b * n, c->mD32 + b * n, c->mP32 + b * n,
+                                        c->mscal + b * S_COUNT + S_ALPHA, n, s));
+    }
     return NM_OK;
 }
 
@@ -803,18 +906,23 @@ int build_green(nm_ctx* c, const double* G_in)
         std::memcpy(c->G.data(), G_in, c->G.size() * sizeof(double));
         HIPCHK(c, hipMemcpy(c->Gdev, cm.data(), cm.size() * sizeof(double), hipMemcpyHostToDevice));
     } else if (int nb = green_batch_size(c); nb >= 2) {
-        // nb unit-force solves at a time (FP64), each column as a single solve would give it
+        // nb unit-force solves at a time in the context's precision
+        const bool mixed = c->opt.precision == NM_PREC_MIXED;
         if (c->mnb < nb) {
             const long cs = c->lay.cs;
-            const int npa = xfwd_blocks(c->n1, 3L * c->n2 * c->n3);
-            const int npb = std::max(xinv_blocks(c->n1, 3L * c->n2 * c->n3), zprecond_blocks<double>(c->sp));
-            CHK(dalloc(c, &c->mX, nb * n));
-            CHK(dalloc(c, &c->mR, nb * n));
-            CHK(dalloc(c, &c->mP, nb * n));
-            CHK(dalloc(c, &c->mQ, nb * n));
+            const long lpf = 3L * c->n2 * c->n3;
+            const int npa = xfwd_blocks(c->n1, lpf);
+            const int npb = std::max({xinv_blocks(c->n1, lpf), zprecond_blocks<double>(c->sp),
+                                      zprecond_blocks<float>(c->sp)});
+            for (double** f : {&c->mX, &c->mR, &c->mP, &c->mQ, &c->mB}) CHK(dalloc(c, f, nb * n));
             CHK(dalloc(c, &c->mU, 3 * (size_t)nb));
             CHK(dalloc(c, &c->mS, nb * 6 * cs));
             CHK(dalloc(c, &c->mS2, nb * 6 * cs));
+            if (mixed) {
+                for (float** f : {&c->mD32, &c->mR32, &c->mP32, &c->mQ32}) CHK(dalloc(c, f, nb * n));
+                CHK(dalloc(c, &c->mS32, nb * 6 * cs));
+                CHK(dalloc(c, &c->mS2_32, nb * 6 * cs));
+            }
             CHK(dalloc(c, &c->mpa, (size_t)nb * npa));
             CHK(dalloc(c, &c->mpb, (size_t)nb * npb));
             CHK(dalloc(c, &c->mscal, (size_t)nb * S_COUNT));
@@ -824,14 +932,14 @@ int build_green(nm_ctx* c, const double* G_in)
         std::vector<double> units(3 * (size_t)nb);
         for (long col0 = 0; col0 < nd; col0 += nb) {
             const int kk = (int)std::min<long>(nb, nd - col0);
-            LCHK(c, launch_fill<double>(c->mR, 0.0, kk * n, s));
+            LCHK(c, launch_fill<double>(c->mB, 0.0, kk * n, s));
             std::fill(units.begin(), units.end(), 0.0);
             for (int b = 0; b < kk; b++) units[3 * b + (col0 + b) % d] = 1.0;
             HIPCHK(c, hipMemcpyAsync(c->mU, units.data(), 3 * kk * sizeof(double), hipMemcpyHostToDevice, s));
             for (int b = 0; b < kk; b++)
-                LCHK(c, launch_set_gamma(c->mR + b * n, c->gidx + (col0 + b) / d, 1, c->mU + 3 * b, 0, 3, c->N, s));
+                LCHK(c, launch_set_gamma(c->mB + b * n, c->gidx + (col0 + b) / d, 1, c->mU + 3 * b, 0, 3, c->N, s));
             int its = 0;
-            CHK(pcg_multi(c, kk, c->opt.green_tol, &its));
+            CHK(solve_multi(c, kk, c->opt.green_tol, &its));
             for (int b = 0; b < kk; b++) {
                 LCHK(c, launch_gather_gamma(c->gbuf, c->mX + b * n, c->gidx, c->ng, 3, c->N, s));
                 LCHK(c, launch_green_column(c->Gdev, nd, col0 + b, c->gbuf, c->ng, d, s));
@@ -840,9 +948,12 @@ int build_green(nm_ctx* c, const double* G_in)
             if (c->opt.green_progress) c->opt.green_progress(col0 + kk, nd, c->opt.green_progress_user);
         }
         // the solve buffers are needed only here
-        for (double** f : {&c->mX, &c->mR, &c->mP, &c->mQ, &c->mU, &c->mpa, &c->mpb, &c->mscal}) dfree(c, f);
+        for (double** f : {&c->mX, &c->mR, &c->mP, &c->mQ, &c->mB, &c->mU, &c->mpa, &c->mpb, &c->mscal}) dfree(c, f);
+        for (float** f : {&c->mD32, &c->mR32, &c->mP32, &c->mQ32}) dfree(c, f);
         dfree(c, &c->mS);
         dfree(c, &c->mS2);
+        dfree(c, &c->mS32);
+        dfree(c, &c->mS2_32);
         (void)hipHostFree(c->mhscal);
         c->mhscal = nullptr;
         c->mnb = 0;

@@ -103,22 +103,25 @@ def test_mixed_precision_green_route():
     assert all(x["relres"] > 0 for x in st[1:])
 
 
-@pytest.mark.parametrize("case", ["polycrystal-16-sphere", "disc2d", "spheres-32-slab"])
+@pytest.mark.parametrize("case", ["polycrystal-16-sphere", "disc2d", "spheres-32-slab", "spheres-32-slab-mixed"])
 def test_unit_force_solves_run_together(case):
     """Several unit-force solves through one chain of kernels (fields side by side, each loop
     with its own scalars, frozen once converged) give the Green matrix the one-at-a-time solves
-    give (FP64), and the same trajectory."""
+    give: bit for bit in FP64; in mixed precision (FP64 refinement of FP32 corrections, fields
+    whose FP64 residual has converged frozen in later corrections) to the unit-force tolerance."""
     import time
     if case == "disc2d":
         pb = W.make_disc2d()
-    elif case == "spheres-32-slab":
+    elif case.startswith("spheres-32-slab"):
         pb = W.make_spheres3d(n=32, seed=2)
     else:
         pb = W.make_polycrystal(n=16, n_grains=6, seed=7, gamma="sphere", sphere_radius=1.5)
     nd = pb.dim * pb.gamma_idx.size
     res = {}
     for batch in (1, 0, 5):
-        opts = nmb.Options(tol=1e-10, max_iter=800, route=nmb.ROUTE_GREEN, green_tol=1e-12, green_batch=batch)
+        prec = nmb.PREC_MIXED if case.endswith("mixed") else nmb.PREC_FP64
+        opts = nmb.Options(tol=1e-10, max_iter=800, route=nmb.ROUTE_GREEN, green_tol=1e-12, green_batch=batch,
+                           precision=prec)
         t0 = time.perf_counter()
         with nmb.newmark_init_problem(pb, opts) as ctx:
             t_init = time.perf_counter() - t0
@@ -134,4 +137,7 @@ def test_unit_force_solves_run_together(case):
         eu = float(np.abs(u - u1).max() / np.abs(u1).max())
         print(f"{case}: {nd} unit-force solves, one at a time {t1:.2f} s, batch {batch or 'auto'} {t:.2f} s; "
               f"G max rel diff {eg:.1e}, u {eu:.1e}", flush=True)
-        assert eg <= 1e-13 and eu <= 1e-12
+        if case.endswith("mixed"):
+            assert eg <= 1e-10 and eu <= 1e-9
+        else:
+            assert eg <= 1e-13 and eu <= 1e-12
