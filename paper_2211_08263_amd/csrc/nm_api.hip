@@ -85,7 +85,7 @@ struct nm_ctx {
     double* Gdev = nullptr;        // G, then its LU factors (column major, d n_gamma square)
     int* pivdev = nullptr;         // row swaps of the factorization
     int* permdev = nullptr;        // the swaps composed into one row permutation
-    double* dinvdev = nullptr;     // inverted diagonal blocks of the factors (per 64-column panel)
+    double* dinvdev = nullptr;     // inverted 256 x 256 diagonal blocks of the factors
     double* luwork = nullptr;      // 2 x (d n_gamma) work vector of the substitutions
     int* singdev = nullptr;        // set by the factorization on a zero pivot
     int green_sweeps = 0, green_inner = 0; // mixed-precision Green route: running totals
@@ -722,8 +722,8 @@ int multi_operator_rest(nm_ctx* c, const MultiLayout& L, int nb, const MultiBufs
 // On return every x_b still lacks its deferred last alpha p (alpha is zero for the loops
 // frozen before the last iteration); c->mhscal holds the final scalars.
 template <typename T>
-int pcg_multi_core(nm_ctx* c, int nb, const MultiBufs<T>& m, const double* rr, const double* thr2,
-                   const bool* frozen, int max_iter, int* iters_max)
+int pcg_multi_core(nm_ctx* c, int nb, const MultiBufs<T>& m, const double* thr2, const bool* frozen, int max_iter,
+                   int* iters_max)
 {
     hipStream_t s = c->stream;
     const long n = 3 * c->N;
@@ -733,7 +733,6 @@ int pcg_multi_core(nm_ctx* c, int nb, const MultiBufs<T>& m, const double* rr, c
     for (int b = 0; b < nb; b++) {
         LCHK(c, launch_loop_init(c->mscal + b * S_COUNT, thr2[b], max_iter, 0, s));
         if (frozen[b]) LCHK(c, launch_fill<double>(c->mscal + b * S_COUNT + S_STOP, 1.0, 1, s));
-        (void)rr;
     }
     LCHK(c, launch_fill<T>(m.x, (T)0, nb * n, s));
     // z = M r as its x spectrum, r.z
@@ -843,7 +842,7 @@ int solve_multi(nm_ctx* c, int nb, double tol, int* iters_max)
     if (c->opt.precision != NM_PREC_MIXED) {
         for (int b = 0; b < nb; b++) thr2[b] = tol * tol * rr[b];
         const bool none[64] = {};
-        CHK(pcg_multi_core<double>(c, nb, m64, rr.data(), thr2.data(), none, c->opt.max_iter, iters_max));
+        CHK(pcg_multi_core<double>(c, nb, m64, thr2.data(), none, c->opt.max_iter, iters_max));
         // the deferred last x += alpha p (zero for the loops frozen before the last iteration)
         for (int b = 0; b < nb; b++) {
             if (!(c->mhscal[b * S_COUNT + S_RR] <= thr2[b]))
@@ -869,7 +868,7 @@ int solve_multi(nm_ctx* c, int nb, double tol, int* iters_max)
         if (all) break;
         if (sweep >= c->opt.max_sweeps)
             return fail(c, NM_ENOTCONV, "mixed precision did not reach tol %.3g in %d sweeps", tol, sweep);
-        CHK(pcg_multi_core<float>(c, nb, m32, rr.data(), thr2.data(), frozen, c->opt.max_iter, iters_max));
+        CHK(pcg_multi_core<float>(c, nb, m32, thr2.data(), frozen, c->opt.max_iter, iters_max));
         // X += D + alpha P (the correction's deferred last update folded in FP64)
         for (int b = 0; b < nb; b++)
             LCHK(c, launch_add_f2d_axpy(c->mX + b * n, c->mD32 + b * n, c->mP32 + b * n,
@@ -891,7 +890,7 @@ int build_green(nm_ctx* c, const double* G_in)
     CHK(dalloc(c, &c->Gdev, (size_t)nd * nd));
     CHK(dalloc(c, &c->pivdev, nd));
     CHK(dalloc(c, &c->permdev, nd));
-    CHK(dalloc(c, &c->dinvdev, (size_t)((nd + 63) / 64) * 2 * 64 * 64));
+    CHK(dalloc(c, &c->dinvdev, (size_t)((nd + 255) / 256) * 2 * 256 * 256));
     CHK(dalloc(c, &c->luwork, 2 * (size_t)nd));
     CHK(dalloc(c, &c->singdev, 1));
     c->G.assign((size_t)nd * nd, 0.0);

@@ -10,7 +10,7 @@ namespace nm {
 // row j at step j.  *sing (device) is set to 1 when a pivot is zero.  Asynchronous.
 int lu_factor_device(double* A, int n, int* piv, int* sing, hipStream_t s);
 // After lu_factor_device: the pivots composed into one row permutation (perm, n ints) and the
-// inverses of the diagonal blocks of every panel (dinv, 2 * 64 * 64 doubles per 64 columns), so
+// inverses of the 256 x 256 diagonal blocks (dinv, 2 * 256 * 256 doubles per 256 columns), so
 // that a solve is one gather and one launch per panel and direction.  Asynchronous.
 int lu_prepare_solve(const double* LU, int n, const int* piv, int* perm, double* dinv, hipStream_t s);
 // b <- A^-1 b with those factors; work: 2 n doubles.  Asynchronous.

@@ -9,14 +9,17 @@
 //   row swaps of the panel applied to the columns outside it (one thread per column);
 //   U12 = L11^-1 A12 (forward substitution, one thread per column);
 //   A22 -= L21 U12 (tiled FP64 GEMM, 64 x 64 tiles staged through LDS).
-// Solves: pivots, then blocked forward (unit L) and backward (U) substitution with a
-// one-block triangle solve per kNb rows and a matrix-vector update of the rest.
+// Solves: the pivots composed into one permutation (a gather), then blocked forward (unit L)
+// and backward (U) substitution in panels of kSb rows, one launch per panel: every block forms
+// the panel's solution from the inverted kSb x kSb diagonal block (inverted once after the
+// factorization) and updates its share of the remaining rows.
 #include "nm_common.h"
 #include "nm_green.h"
 
 namespace nm {
 
-constexpr int kNb = 64;    // panel width
+constexpr int kNb = 64;    // panel width of the factorization
+constexpr int kSb = 256;   // panel width of the substitutions (inverted diagonal blocks)
 constexpr int kGT = 64;    // GEMM tile (rows and columns of C per block)
 
 // Pivot search in column j (rows j..n-1) and swap of rows j and p inside the panel
@@ -199,47 +202,55 @@ __global__ void k_lu_perm_from_piv(const int* __restrict__ piv, int* __restrict_
     }
 }
 
-// Inverses of the diagonal blocks of one panel (block per panel, kNb threads; thread j
-// forms column j): dinv[0 .. kNb^2) = L_kk^-1 (unit lower), dinv[kNb^2 .. 2 kNb^2) = U_kk^-1,
-// row major, zero outside the triangle.
-__global__ __launch_bounds__(kNb) void k_lu_diag_inv(const double* __restrict__ A, int n, double* __restrict__ dinv)
+// Inverses of the kSb x kSb diagonal blocks of the factors (block per diagonal block, kSb
+// threads; thread j forms column j): dinv[0 .. kSb^2) = L_kk^-1 (unit lower),
+// dinv[kSb^2 .. 2 kSb^2) = U_kk^-1, column major (entry (i, j) at j kSb + i), zero outside the
+// triangle.  The rows of the factors are swept in order, each staged once in LDS for all
+// columns.
+__global__ __launch_bounds__(kSb) void k_lu_diag_inv(const double* __restrict__ A, int n, double* __restrict__ dinv)
 {
-    const int k0 = blockIdx.x * kNb;
-    const int kb = n - k0 < kNb ? n - k0 : kNb;
+    __shared__ double row[kSb];
+    const int k0 = blockIdx.x * kSb;
+    const int kb = n - k0 < kSb ? n - k0 : kSb;
     const int j = threadIdx.x;
-    double* Li = dinv + (long)blockIdx.x * 2 * kNb * kNb;
-    double* Ui = Li + kNb * kNb;
-    for (int i = 0; i < kNb; i++) {
-        Li[i * kNb + j] = 0.0;
-        Ui[i * kNb + j] = 0.0;
+    double* Lj = dinv + (long)blockIdx.x * 2 * kSb * kSb + (long)j * kSb; // column j of L_kk^-1
+    double* Uj = Lj + kSb * kSb;                                           // column j of U_kk^-1
+    for (int i = 0; i < kSb; i++) {
+        Lj[i] = 0.0;
+        Uj[i] = 0.0;
     }
-    if (j >= kb) return;
-    // L x = e_j: x_i = -sum_{j <= q < i} L_iq x_q below the unit diagonal
-    double x[kNb];
-    for (int i = 0; i < kNb; i++) x[i] = 0.0;
-    x[j] = 1.0;
-    for (int i = j + 1; i < kb; i++) {
-        double acc = 0.0;
-        for (int q = j; q < i; q++) acc += A[(long)(k0 + q) * n + (k0 + i)] * x[q];
-        x[i] = -acc;
+    // L x = e_j: x_j = 1, x_i = -sum_{j <= q < i} L_iq x_q for i > j (row i of L staged)
+    if (j < kb) Lj[j] = 1.0;
+    for (int i = 1; i < kb; i++) {
+        __syncthreads();
+        if (j < i) row[j] = A[(long)(k0 + j) * n + (k0 + i)];
+        __syncthreads();
+        if (j < i) {
+            double acc = 0.0;
+            for (int q = j; q < i; q++) acc += row[q] * Lj[q];
+            Lj[i] = -acc;
+        }
     }
-    for (int i = j; i < kb; i++) Li[i * kNb + j] = x[i];
-    // U x = e_j: x_j = 1 / U_jj, x_i = -(sum_{i < q <= j} U_iq x_q) / U_ii above it
-    for (int i = 0; i < kNb; i++) x[i] = 0.0;
-    x[j] = 1.0 / A[(long)(k0 + j) * n + (k0 + j)];
-    for (int i = j - 1; i >= 0; i--) {
-        double acc = 0.0;
-        for (int q = i + 1; q <= j; q++) acc += A[(long)(k0 + q) * n + (k0 + i)] * x[q];
-        x[i] = -acc / A[(long)(k0 + i) * n + (k0 + i)];
+    // U x = e_j: x_j = 1 / U_jj, x_i = -(sum_{i < q <= j} U_iq x_q) / U_ii for i < j (row i of U
+    // staged, rows from the bottom)
+    if (j < kb) Uj[j] = 1.0 / A[(long)(k0 + j) * n + (k0 + j)];
+    for (int i = kb - 2; i >= 0; i--) {
+        __syncthreads();
+        if (j >= i && j < kb) row[j] = A[(long)(k0 + j) * n + (k0 + i)];
+        __syncthreads();
+        if (j > i && j < kb) {
+            double acc = 0.0;
+            for (int q = i + 1; q <= j; q++) acc += row[q] * Uj[q];
+            Uj[i] = -acc / row[i];
+        }
     }
-    for (int i = 0; i <= j; i++) Ui[i * kNb + j] = x[i];
 }
 
 int lu_prepare_solve(const double* LU, int n, const int* piv, int* perm, double* dinv, hipStream_t s)
 {
     hipLaunchKernelGGL(k_lu_perm_from_piv, dim3(1), dim3(1), 0, s, piv, perm, n);
-    const int np = (n + kNb - 1) / kNb;
-    hipLaunchKernelGGL(k_lu_diag_inv, dim3(np), dim3(kNb), 0, s, LU, n, dinv);
+    const int np = (n + kSb - 1) / kSb;
+    hipLaunchKernelGGL(k_lu_diag_inv, dim3(np), dim3(kSb), 0, s, LU, n, dinv);
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
 
@@ -254,17 +265,20 @@ __global__ __launch_bounds__(256) void k_lu_gather(const double* __restrict__ b,
 // (every block forms it; block 0 stores it in out[k0:k1]), then in[r] -= A[r, k0:k1] x_k for
 // the rows r in [r0, r1) (one thread per row).  Those rows lie outside [k0, k1), so no block
 // reads an entry another block writes.
-__global__ __launch_bounds__(256) void k_tri_panel(const double* __restrict__ A, int n, const double* __restrict__ D,
+__global__ __launch_bounds__(kSb) void k_tri_panel(const double* __restrict__ A, int n, const double* __restrict__ D,
                                                    double* __restrict__ in, double* __restrict__ out, int k0, int k1,
                                                    int r0, int r1)
 {
-    __shared__ double xs[kNb];
+    __shared__ double xs[kSb];
+    __shared__ double bk[kSb];
     const int t = threadIdx.x;
     const int kb = k1 - k0;
-    if (t < kNb) {
+    bk[t] = t < kb ? in[k0 + t] : 0.0;
+    __syncthreads();
+    {
         double acc = 0.0;
         if (t < kb)
-            for (int q = 0; q < kb; q++) acc += D[t * kNb + q] * in[k0 + q];
+            for (int q = 0; q < kb; q++) acc += D[q * kSb + t] * bk[q];
         xs[t] = acc;
     }
     __syncthreads();
@@ -283,17 +297,17 @@ int lu_solve_device(const double* LU, int n, const int* perm, const double* dinv
     double* w = work;      // P b, then the forward residuals
     double* y = work + n;  // L^-1 P b, then the backward residuals
     hipLaunchKernelGGL(k_lu_gather, dim3((n + 255) / 256), dim3(256), 0, s, b, perm, w, n);
-    const int np = (n + kNb - 1) / kNb;
+    const int np = (n + kSb - 1) / kSb;
     for (int k = 0; k < np; k++) {
-        const int k0 = k * kNb, k1 = k0 + kNb < n ? k0 + kNb : n;
+        const int k0 = k * kSb, k1 = k0 + kSb < n ? k0 + kSb : n;
         const int rows = n - k1;
-        hipLaunchKernelGGL(k_tri_panel, dim3(rows > 0 ? (rows + 255) / 256 : 1), dim3(256), 0, s, LU, n,
-                           dinv + (long)k * 2 * kNb * kNb, w, y, k0, k1, k1, n);
+        hipLaunchKernelGGL(k_tri_panel, dim3(rows > 0 ? (rows + kSb - 1) / kSb : 1), dim3(kSb), 0, s, LU, n,
+                           dinv + (long)k * 2 * kSb * kSb, w, y, k0, k1, k1, n);
     }
     for (int k = np - 1; k >= 0; k--) {
-        const int k0 = k * kNb, k1 = k0 + kNb < n ? k0 + kNb : n;
-        hipLaunchKernelGGL(k_tri_panel, dim3(k0 > 0 ? (k0 + 255) / 256 : 1), dim3(256), 0, s, LU, n,
-                           dinv + (long)k * 2 * kNb * kNb + kNb * kNb, y, b, k0, k1, 0, k0);
+        const int k0 = k * kSb, k1 = k0 + kSb < n ? k0 + kSb : n;
+        hipLaunchKernelGGL(k_tri_panel, dim3(k0 > 0 ? (k0 + kSb - 1) / kSb : 1), dim3(kSb), 0, s, LU, n,
+                           dinv + (long)k * 2 * kSb * kSb + kSb * kSb, y, b, k0, k1, 0, k0);
     }
     return hipGetLastError() == hipSuccess ? 0 : -2;
 }
