@@ -595,8 +595,10 @@ int solve_mixed(nm_ctx* c, double* x, double bref, nm_step_stats* st, double rr_
 // Mixed precision without a Gamma projection (the Green route's solves): FP64 residual
 // r = rhs - A x, FP32 PCG correction, x += d, until ||r|| <= tol bref.
 // rr_out / rr0_out (or null): the last and the first FP64 residual, squared.
+// guard_zero: an initial iterate whose residual exceeds ||rhs|| (the zero start's) is replaced
+// by the zero start.
 int solve_mixed_plain(nm_ctx* c, const double* rhs, double* x, double bref, double tol, bool x_zero, int* sweeps_out,
-                      int* inner_out, double* rr_out = nullptr, double* rr0_out = nullptr)
+                      int* inner_out, double* rr_out = nullptr, double* rr0_out = nullptr, bool guard_zero = false)
 {
     hipStream_t s = c->stream;
     const long n = 3 * c->N;
@@ -609,8 +611,18 @@ int solve_mixed_plain(nm_ctx* c, const double* rhs, double* x, double bref, doub
         LCHK(c, launch_residual<double>(rhs, c->q, c->r, nullptr, c->N, 3, c->part_a, s, c->r32));
         LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
         CHK(read_scalars(c));
-        const double rr = c->hscal[S_RR];
+        double rr = c->hscal[S_RR];
         if (!std::isfinite(rr)) return fail(c, NM_ENAN, "non-finite residual in refinement sweep %d", sweeps);
+        if (sweeps == 0 && guard_zero && !x_zero && rr > bref * bref) {
+            // restart from zero: r = rhs
+            LCHK(c, launch_fill<double>(x, 0.0, n, s));
+            LCHK(c, launch_fill<double>(c->q, 0.0, n, s));
+            LCHK(c, launch_residual<double>(rhs, c->q, c->r, nullptr, c->N, 3, c->part_a, s, c->r32));
+            LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, s));
+            CHK(read_scalars(c));
+            rr = c->hscal[S_RR];
+            c->ws_rejected++;
+        }
         if (sweeps == 0 && rr0_out) *rr0_out = rr;
         if (rr_out) *rr_out = rr;
         if (std::sqrt(rr) <= tol * bref) break;
@@ -633,14 +645,33 @@ int solve_mixed_plain(nm_ctx* c, const double* rhs, double* x, double bref, doub
 // One solve of the Green route (A x = rhs to tol relative to bref, no projection) in the
 // context's precision; mixed precision adds its sweeps and FP32 iterations to the
 // context's running totals.
-int green_solve(nm_ctx* c, const double* rhs, double* x, double bref, double tol, bool x_zero, PcgResult* res)
+// guard_zero (with bref = ||rhs||): an initial iterate whose residual exceeds ||rhs|| is
+// replaced by the zero start (the learned start's guard on the Green route's u_b solve).
+int green_solve(nm_ctx* c, const double* rhs, double* x, double bref, double tol, bool x_zero, PcgResult* res,
+                bool guard_zero = false)
 {
     if (c->opt.precision == NM_PREC_MIXED) {
         *res = PcgResult{};
         res->converged = true;
-        return solve_mixed_plain(c, rhs, x, bref, tol, x_zero, &c->green_sweeps, &c->green_inner, &res->rr, &res->rr0);
+        return solve_mixed_plain(c, rhs, x, bref, tol, x_zero, &c->green_sweeps, &c->green_inner, &res->rr, &res->rr0,
+                                 guard_zero);
     }
-    return pcg<double>(c, rhs, x, c->r, c->p, c->q, false, x_zero, bref, tol, c->opt.max_iter, -1, false, res);
+    double rr0 = -1.0;
+    if (guard_zero && !x_zero) {
+        const long n = 3 * c->N;
+        CHK(apply_A<double>(c, x, c->q, nullptr));
+        LCHK(c, launch_residual<double>(rhs, c->q, c->r, nullptr, c->N, 3, c->part_a, c->stream));
+        LCHK(c, launch_reduce(c->part_a, vec_blocks(n), c->scal, RED_STORE_RR, 0, c->stream));
+        CHK(read_scalars(c));
+        rr0 = c->hscal[S_RR];
+        if (rr0 > bref * bref) {
+            LCHK(c, launch_fill<double>(x, 0.0, n, c->stream));
+            LCHK(c, launch_copy<double>(c->r, rhs, n, c->stream));
+            rr0 = bref * bref;
+            c->ws_rejected++;
+        }
+    }
+    return pcg<double>(c, rhs, x, c->r, c->p, c->q, false, x_zero, bref, tol, c->opt.max_iter, -1, false, res, rr0);
 }
 
 // Fields solved together by the Green route's unit-force solves: enough to give the kernels
@@ -1480,7 +1511,8 @@ static int step_impl(nm_ctx* c, const double* U_n, int per_point, nm_step_stats*
         CHK(norm2<double>(c, c->b, &bn));
         PcgResult r1, r2;
         c->green_sweeps = c->green_inner = 0;
-        CHK(green_solve(c, c->b, c->w, std::sqrt(bn), c->opt.tol, false, &r1));
+        // (a learned iterate further from the solution than zero is replaced by zero)
+        CHK(green_solve(c, c->b, c->w, std::sqrt(bn), c->opt.tol, false, &r1, c->opt.warm_start == NM_WS_LEARNED));
         // V = U - u_b on Gamma ; F = G^-1 V / (beta dt^2)   (eqs. Vt, L-determination_ND), on
         // the device: Fdev holds V, then F (d per point), gbuf the force with 3 components
         LCHK(c, launch_gather_gamma(c->gbuf, c->w, c->gidx, c->ng, 3, c->N, s));

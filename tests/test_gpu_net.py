@@ -482,3 +482,34 @@ def test_learned_start_worse_than_zero_is_replaced_by_the_zero_start(precision):
     assert all(abs(a - b) <= 1 for a, b in zip(it["learned"], it["cold"]))
     assert max(x["relres"] for x in res["learned"][0]) <= 1e-9
     assert err <= 1e-7
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_learned_start_guard_on_the_green_route(precision):
+    """The same guard on the Green route's u_b solve (residual against ||b||, the zero start's):
+    with a nonsense network no step starts further away than zero, and the trajectory agrees
+    with the zero-start Green route to the tolerance."""
+    pb = W.make_polycrystal(n=16, n_grains=6, seed=7, gamma="sphere", sphere_radius=1.5, n_steps=8)
+    net = nmb.Net(seed=5)
+    net.set_params(net.get_params() * 100.0)
+    prec = nmb.PREC_MIXED if precision == "mixed" else nmb.PREC_FP64
+    res = {}
+    for name, ws in (("cold", nmb.WS_COLD), ("learned", nmb.WS_LEARNED)):
+        opts = nmb.Options(tol=1e-10, max_iter=500, warm_start=ws, precision=prec, route=nmb.ROUTE_GREEN,
+                           green_tol=1e-12)
+        with nmb.newmark_init_problem(pb, opts) as ctx:
+            if ws == nmb.WS_LEARNED:
+                nmb.ws_attach(ctx, net)
+            st, us = [], []
+            for s in range(6):
+                st.append(nmb.newmark_step(ctx, pb.U(s + 1)))
+                us.append(nmb.get_state(ctx)["u"].copy())
+        res[name] = (st, us)
+    net.close()
+    r0 = [x["relres0"] for x in res["learned"][0]]
+    err = max(np.linalg.norm(a - b) / max(np.linalg.norm(a), 1e-300)
+              for a, b in zip(res["cold"][1], res["learned"][1]) if np.abs(a).max() > 0)
+    print(f"Green route, {precision}: nonsense network, initial residuals {np.round(r0, 6).tolist()}, rel L2 to "
+          f"the zero-start run {err:.2e}", flush=True)
+    assert all(r <= 1.0 + 1e-6 for r in r0)
+    assert err <= 1e-8
