@@ -9,7 +9,8 @@
 * a context created on a caller's non-default stream with a non-zero initial state holds
   that state (nm_newmark_init queues its zero fills on that stream before the copies);
 * the reaction on Gamma (projected route with compute_reaction, and the Green route's
-  G^-1 V / (beta dt^2)) and the Taylor initial iterate against the oracle.
+  G^-1 V / (beta dt^2)) and the Taylor initial iterate against the oracle;
+* an empty Gamma (free vibration from a random initial state) against the oracle.
 The error paths that fail before any device work are in test_abi.py (CPU).
 """
 import numpy as np
@@ -173,3 +174,35 @@ def test_taylor_start_matches_oracle():
     errs = [rel_l2(u_gpu[s], ref["u"][s]) for s in range(steps) if np.abs(ref["u"][s]).max() > 0]
     print(f"taylor start: iters {its}, max rel L2 {max(errs):.2e}", flush=True)
     assert max(errs) <= 1e-10
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_free_vibration_without_gamma_matches_oracle(precision):
+    """Empty Gamma (n_gamma = 0): free vibration of a heterogeneous anisotropic medium from a
+    random initial state (projected route with nothing to project; the reference residual is
+    then ||b||) against the oracle, FP64 with the oracle replaying the GPU's iterations (1e-10)
+    and mixed precision (1e-5 of the FP64 oracle)."""
+    import dataclasses
+    rng = np.random.default_rng(21)
+    pb = dataclasses.replace(W.make_polycrystal(n=16, n_grains=6, seed=21), gamma_idx=np.zeros(0, np.int64))
+    u0 = rng.standard_normal((3,) + pb.phase_id.shape)
+    v0 = rng.standard_normal((3,) + pb.phase_id.shape)
+    steps = 6
+    prec = nmb.PREC_MIXED if precision == "mixed" else nmb.PREC_FP64
+    us, its = [], []
+    with nmb.newmark_init_problem(pb, nmb.Options(tol=1e-10, max_iter=500, precision=prec), u0=u0, v0=v0) as ctx:
+        for s in range(steps):
+            st = nmb.newmark_step(ctx, np.zeros(3))
+            its.append([st["iters"][0], -1])
+            us.append(nmb.get_state(ctx)["u"].copy())
+    op = oracle.OracleProblem.from_problem(pb)
+    U = np.zeros((steps, 3))
+    if precision == "fp64":
+        ref = op.newmark(pb.gamma_idx, U, steps, replay=np.array(its), u0=u0, v0=v0)
+        bar = 1e-10
+    else:
+        ref = op.newmark(pb.gamma_idx, U, steps, tol=1e-13, u0=u0, v0=v0)
+        bar = 1e-5
+    e = max(rel_l2(us[s], ref["u"][s]) for s in range(steps))
+    print(f"no Gamma, {precision}: iterations {[i[0] for i in its]}, max rel L2 {e:.2e}", flush=True)
+    assert e <= bar
