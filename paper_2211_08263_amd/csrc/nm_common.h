@@ -29,6 +29,33 @@ template <int DIR, typename V> __device__ __forceinline__ V mul_di(V a)
 }
 template <typename V, typename S> __device__ __forceinline__ V cscale(V a, S s) { return V{a.x * s, a.y * s}; }
 
+// Streaming access of a complex element read or written once by a pass: NT bit 0 marks the
+// load nontemporal, bit 1 the store (a cache-policy hint; the values are unchanged).
+template <int NT, typename V> __device__ __forceinline__ V ld_nt(const V* p)
+{
+    if constexpr ((NT & 1) != 0) {
+        using E = decltype(V{}.x);
+        typedef E N2 __attribute__((ext_vector_type(2)));
+        const N2 r = __builtin_nontemporal_load((const N2*)p);
+        return V{r.x, r.y};
+    } else {
+        return *p;
+    }
+}
+template <int NT, typename V> __device__ __forceinline__ void st_nt(V* p, V v)
+{
+    if constexpr ((NT & 2) != 0) {
+        using E = decltype(V{}.x);
+        typedef E N2 __attribute__((ext_vector_type(2)));
+        N2 r;
+        r.x = v.x;
+        r.y = v.y;
+        __builtin_nontemporal_store(r, (N2*)p);
+    } else {
+        *p = v;
+    }
+}
+
 // Spatial frequency of DFT index k on an axis of n points, box length L.
 // Standard DFT order; the Nyquist bin (k = n/2) and n == 1 give 0.
 __host__ __device__ __forceinline__ double freq_of(int k, int n, double L)

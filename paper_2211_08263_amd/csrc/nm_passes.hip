@@ -57,6 +57,55 @@
 #ifndef NM_STRESS512_R64
 #define NM_STRESS512_R64 NM_STRESS_R64
 #endif
+// Nontemporal (streaming) loads (bit 0) and stores (bit 1) of the spectra and fields that a
+// pass reads or writes once, per pass family and precision.  Measured at 256^3 (500 grains):
+// FP64 operator 1.72 -> 1.63 ms, preconditioner 0.91 -> 0.84 ms, Newmark step 40.7 -> 38.0 ms;
+// the FP32 passes gain less and lose where the preconditioner's column passes stream their
+// loads (0.43 -> 0.48 ms), so FP32 streams only the x passes and the column operators' stores
+// (mixed-precision step 24.3 -> 23.2 ms).
+#ifndef NM_STRESS_NT64
+#define NM_STRESS_NT64 3
+#endif
+#ifndef NM_STRESS_NT32
+#define NM_STRESS_NT32 3
+#endif
+#ifndef NM_XFWD_NT64
+#define NM_XFWD_NT64 3
+#endif
+#ifndef NM_XFWD_NT32
+#define NM_XFWD_NT32 3
+#endif
+#ifndef NM_XINV_NT64
+#define NM_XINV_NT64 3
+#endif
+#ifndef NM_XINV_NT32
+#define NM_XINV_NT32 3
+#endif
+#ifndef NM_XPUP_NT64
+#define NM_XPUP_NT64 3
+#endif
+#ifndef NM_XPUP_NT32
+#define NM_XPUP_NT32 3
+#endif
+#ifndef NM_YPASS_NT64
+#define NM_YPASS_NT64 2
+#endif
+#ifndef NM_YPASS_NT32
+#define NM_YPASS_NT32 0
+#endif
+#ifndef NM_COLOP_NT64
+#define NM_COLOP_NT64 3
+#endif
+#ifndef NM_COLOP_NT32
+#define NM_COLOP_NT32 2
+#endif
+#ifndef NM_ZPRE_NT64
+#define NM_ZPRE_NT64 2
+#endif
+#ifndef NM_ZPRE_NT32
+#define NM_ZPRE_NT32 0
+#endif
+#define NM_NT(FAM, T) (sizeof(T) == 8 ? NM_##FAM##_NT64 : NM_##FAM##_NT32)
 
 namespace nm {
 
@@ -152,7 +201,7 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
         if constexpr (MODE == XF_PLAIN) {
             const V* src = (const V*)a.src + off;
 #pragma unroll
-            for (int m = 0; m < R; m++) v[m] = src[t + m * G];
+            for (int m = 0; m < R; m++) v[m] = ld_nt<NM_NT(XFWD, T)>(src + t + m * G);
         } else if constexpr (MODE == XF_EXPLICIT) {
             // u_n = u_{n-1} + dt v_{n-1} + dt^2/2 a_{n-1}   (eq. Central_diff_rule)
             const T dt = (T)a.dt, h2 = (T)(0.5 * a.dt * a.dt);
@@ -175,9 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
 #pragma unroll
             for (int m = 0; m < R; m++) {
                 const int i = t + m * G;
-                V qq = q[i], rr = r[i];
+                V qq = ld_nt<NM_NT(XFWD, T)>(q + i), rr = ld_nt<NM_NT(XFWD, T)>(r + i);
                 rr = V{rr.x - alpha * qq.x, rr.y - alpha * qq.y};
-                r[i] = rr;
+                st_nt<NM_NT(XFWD, T)>(r + i, rr);
                 part += (double)rr.x * (double)rr.x + (double)rr.y * (double)rr.y;
                 v[m] = rr;
             }
@@ -196,7 +245,7 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int k = t + m * G;
-            out[k] = r2c_post(k, v[m], mir[m], twN[k]);
+            st_nt<NM_NT(XFWD, T)>(out + k, r2c_post(k, v[m], mir[m], twN[k]));
         }
     }
     if constexpr (MODE == XF_UPDATE) {
@@ -226,7 +275,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
     V v[R];
     const long soff = a.lay.line(line);
 #pragma unroll
-    for (int m = 0; m < R; m++) v[m] = valid ? ((const V*)a.spec)[soff + t + m * G] : V{0, 0};
+    for (int m = 0; m < R; m++) v[m] = valid ? ld_nt<NM_NT(XINV, T)>((const V*)a.spec + soff + t + m * G) : V{0, 0};
     // the real-space operands of the fused stage are fetched before the transform
     V au[R];
     uint32_t ph[R];
@@ -249,7 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int n = t + m * G;
-            au[m] = (valid && a.aux) ? aux[n] : V{0, 0};
+            au[m] = (valid && a.aux) ? ld_nt<NM_NT(XINV, T)>(aux + n) : V{0, 0};
             ph[m] = (valid && MODE == XI_OPERATOR) ? ((const uint32_t*)a.phase)[vline * M + n] : 0u;
             mk[m] = (valid && a.mask) ? ((const uint16_t*)a.mask)[vline * M + n] : (uint16_t)0;
         }
@@ -271,7 +320,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
         V* out = (V*)a.out + off;
         if constexpr (MODE == XI_PLAIN) {
 #pragma unroll
-            for (int m = 0; m < R; m++) out[t + m * G] = v[m];
+            for (int m = 0; m < R; m++) st_nt<NM_NT(XINV, T)>(out + t + m * G, v[m]);
         } else if constexpr (MODE == XI_EXPLICIT) {
             // o = dt/2 div sigma: v <- v + dt/2 a + o / rho, a <- (2/dt) o / rho
             const bool zero_comp = (a.dim == 2) && ((line / a.lines_per_comp) % 3 == 2);
@@ -308,7 +357,7 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
                 if (mk[m] & 0xff00u) o.y = 0;
                 if (zero_comp) o = V{0, 0};
                 part += (double)au[m].x * (double)o.x + (double)au[m].y * (double)o.y;
-                out[n] = o;
+                st_nt<NM_NT(XINV, T)>(out + n, o);
             }
         }
     }
@@ -345,7 +394,7 @@ __global__ __launch_bounds__(kBlock) void k_xpupdate(XInvArgs a, const cx_t<T>* 
     V* spec = (V*)a.spec;
     V v[R];
 #pragma unroll
-    for (int m = 0; m < R; m++) v[m] = valid ? spec[soff + t + m * G] : V{0, 0};
+    for (int m = 0; m < R; m++) v[m] = valid ? ld_nt<NM_NT(XPUP, T)>(spec + soff + t + m * G) : V{0, 0};
     // the real-space operands are fetched before the transforms
     const double* sc = a.scal + ((a.lines_per_batch && valid) ? line / a.lines_per_batch : 0) * S_COUNT;
     const bool first = sc[S_FIRST] != 0.0;
@@ -359,8 +408,8 @@ __global__ __launch_bounds__(kBlock) void k_xpupdate(XInvArgs a, const cx_t<T>* 
 #pragma unroll
     for (int m = 0; m < R; m++) {
         const int n = t + m * G;
-        po[m] = (valid && !first) ? p[n] : V{0, 0};
-        xo[m] = (valid && !first) ? x[n] : V{0, 0};
+        po[m] = (valid && !first) ? ld_nt<NM_NT(XPUP, T)>(p + n) : V{0, 0};
+        xo[m] = (valid && !first) ? ld_nt<NM_NT(XPUP, T)>(x + n) : V{0, 0};
         mk[m] = (valid && a.mask) ? ((const uint16_t*)a.mask)[vline * M + n] : (uint16_t)0;
     }
     LineAddr<R, (int)sizeof(V)> addr{ll * LP};
@@ -392,8 +441,8 @@ __global__ __launch_bounds__(kBlock) void k_xpupdate(XInvArgs a, const cx_t<T>* 
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int n = t + m * G;
-            p[n] = v[m];
-            if (!first) x[n] = xo[m];
+            st_nt<NM_NT(XPUP, T)>(p + n, v[m]);
+            if (!first) st_nt<NM_NT(XPUP, T)>(x + n, xo[m]);
         }
     }
     group_fft<M, R, -1, true>(v, t, lds, addr, twM);
@@ -407,7 +456,7 @@ __global__ __launch_bounds__(kBlock) void k_xpupdate(XInvArgs a, const cx_t<T>* 
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int k = t + m * G;
-            spec[soff + k] = r2c_post(k, v[m], mir[m], twN[k]);
+            st_nt<NM_NT(XPUP, T)>(spec + soff + k, r2c_post(k, v[m], mir[m], twN[k]));
         }
     }
 }
@@ -475,7 +524,7 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
 #pragma unroll
     for (int c = 0; c < PF; c++)
 #pragma unroll
-        for (int m = 0; m < R; m++) raw[c][m] = valid ? spec[c * NS + off + t + m * G] : V{0, 0};
+        for (int m = 0; m < R; m++) raw[c][m] = valid ? ld_nt<NM_NT(STRESS, T)>(spec + c * NS + off + t + m * G) : V{0, 0};
     uint32_t phw[R];
     {
         const uint32_t* ph2 = (const uint32_t*)phase + (valid ? line % lpf : 0) * M;
@@ -490,7 +539,7 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
         for (int m = 0; m < R; m++) v[m] = raw[c][m];
         if (c + PF < 6) {
 #pragma unroll
-            for (int m = 0; m < R; m++) raw[c + PF][m] = valid ? spec[(c + PF) * NS + off + t + m * G] : V{0, 0};
+            for (int m = 0; m < R; m++) raw[c + PF][m] = valid ? ld_nt<NM_NT(STRESS, T)>(spec + (c + PF) * NS + off + t + m * G) : V{0, 0};
         }
 #pragma unroll
         for (int m = 0; m < R; m++) lds[addr(t + m * G)] = v[m];
@@ -541,7 +590,7 @@ __global__ __launch_bounds__(kBlock) void k_xstress(cx_t<T>* spec, SpecLayout la
 #pragma unroll
             for (int m = 0; m < R; m++) {
                 const int k = t + m * G;
-                spec[c * NS + off + k] = r2c_post(k, v[m], mir[m], twk(m, k));
+                st_nt<NM_NT(STRESS, T)>(spec + c * NS + off + k, r2c_post(k, v[m], mir[m], twk(m, k)));
             }
         }
     }
@@ -577,11 +626,11 @@ __global__ __launch_bounds__(BLK) void k_ypass(cx_t<T>* __restrict__ data, long 
     V* col = data + zc + blockIdx.y * planestride + (long)blockIdx.x * TX + c;
     V v[R];
 #pragma unroll
-    for (int m = 0; m < R; m++) v[m] = col[(long)(t + m * G) * colstride];
+    for (int m = 0; m < R; m++) v[m] = ld_nt<NM_NT(YPASS, T)>(col + (long)(t + m * G) * colstride);
     ColAddrT<TXC> addr{c, TX};
     group_fft<L, R, DIR>(v, t, lds, addr, twsm);
 #pragma unroll
-    for (int m = 0; m < R; m++) col[(long)(t + m * G) * colstride] = v[m];
+    for (int m = 0; m < R; m++) st_nt<NM_NT(YPASS, T)>(col + (long)(t + m * G) * colstride, v[m]);
 }
 
 // Frequency of x bin kx (0 <= kx < n1/2; slot 0 also carries the Nyquist bin, zero under every
@@ -635,7 +684,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
 #pragma unroll
         for (int j = 0; j < 3; j++)
 #pragma unroll
-            for (int m = 0; m < R; m++) v[j][m] = at(j, m);
+            for (int m = 0; m < R; m++) v[j][m] = ld_nt<NM_NT(ZPRE, T)>(&at(j, m));
     };
     V u[3][R];
     if constexpr (TXC > 0 && L >= 2 && sizeof(T) == 4) {
@@ -752,7 +801,7 @@ __global__ __launch_bounds__(BLK) void k_zprecond(cx_t<T>* __restrict__ data, lo
     for (int j = 0; j < 3; j++) {
         group_fft<L, R, +1>(u[j], t, lds, addr, twL);
 #pragma unroll
-        for (int m = 0; m < R; m++) at(j, m) = u[j][m];
+        for (int m = 0; m < R; m++) st_nt<NM_NT(ZPRE, T)>(&at(j, m), u[j][m]);
     }
     if (partials) {
         const double pd = (kx == 0 ? 1.0 : 2.0) * (double)part;
@@ -834,21 +883,21 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
     auto ld = [&](const V* base, int comp, V (&v)[R]) {
         const char* p = (const char*)(base + comp * cs);
 #pragma unroll
-        for (int m = 0; m < R; m++) v[m] = *(const V*)(p + (lane + (uint32_t)m * mstep));
+        for (int m = 0; m < R; m++) v[m] = ld_nt<NM_NT(COLOP, T)>((const V*)(p + (lane + (uint32_t)m * mstep)));
     };
     auto st = [&](V* base, int comp, const V (&v)[R]) {
         char* p = (char*)(base + comp * cs);
 #pragma unroll
-        for (int m = 0; m < R; m++) *(V*)(p + (lane + (uint32_t)m * mstep)) = v[m];
+        for (int m = 0; m < R; m++) st_nt<NM_NT(COLOP, T)>((V*)(p + (lane + (uint32_t)m * mstep)), v[m]);
     };
 #else
     auto ld = [&](const V* col, int comp, V (&v)[R]) {
 #pragma unroll
-        for (int m = 0; m < R; m++) v[m] = col[comp * cs + (long)(t + m * G) * step];
+        for (int m = 0; m < R; m++) v[m] = ld_nt<NM_NT(COLOP, T)>(col + comp * cs + (long)(t + m * G) * step);
     };
     auto st = [&](V* col, int comp, const V (&v)[R]) {
 #pragma unroll
-        for (int m = 0; m < R; m++) col[comp * cs + (long)(t + m * G) * step] = v[m];
+        for (int m = 0; m < R; m++) st_nt<NM_NT(COLOP, T)>(col + comp * cs + (long)(t + m * G) * step, v[m]);
     };
 #endif
     // v <- D v along the column (forward FFT, i xi / n, inverse FFT)
