@@ -110,6 +110,42 @@
 // the loads carry no branch (measured: FP32 stress pass 214 -> 206 us at 256^3; the same in FP64
 // costs 30%, so FP64 keeps the guarded loads).
 #define NM_TAIL_LOADS(T) (sizeof(T) == 4)
+// per column operator (ColOp 0..3), defaulting to the family's setting.  The FP32 strain pass
+// (ZOP_STRAIN) streams its loads as well: 170 -> 151 us at 256^3, FP32 operator 0.856 -> 0.838 ms
+// (the same pass's setting moves the FP64 stress pass after it by up to 20 us either way, and the
+// FP64 operator by no more than the noise, so FP64 keeps the family setting).
+#ifndef NM_COLOP2_NT32
+#define NM_COLOP2_NT32 3
+#endif
+#ifndef NM_COLOP0_NT64
+#define NM_COLOP0_NT64 NM_COLOP_NT64
+#endif
+#ifndef NM_COLOP0_NT32
+#define NM_COLOP0_NT32 NM_COLOP_NT32
+#endif
+#ifndef NM_COLOP1_NT64
+#define NM_COLOP1_NT64 NM_COLOP_NT64
+#endif
+#ifndef NM_COLOP1_NT32
+#define NM_COLOP1_NT32 NM_COLOP_NT32
+#endif
+#ifndef NM_COLOP2_NT64
+#define NM_COLOP2_NT64 NM_COLOP_NT64
+#endif
+#ifndef NM_COLOP2_NT32
+#define NM_COLOP2_NT32 NM_COLOP_NT32
+#endif
+#ifndef NM_COLOP3_NT64
+#define NM_COLOP3_NT64 NM_COLOP_NT64
+#endif
+#ifndef NM_COLOP3_NT32
+#define NM_COLOP3_NT32 NM_COLOP_NT32
+#endif
+#define NM_COLOP_OP_NT(OP, T)                                                                                          \
+    ((OP) == 0   ? (sizeof(T) == 8 ? NM_COLOP0_NT64 : NM_COLOP0_NT32)                                                     \
+     : (OP) == 1 ? (sizeof(T) == 8 ? NM_COLOP1_NT64 : NM_COLOP1_NT32)                                                     \
+     : (OP) == 2 ? (sizeof(T) == 8 ? NM_COLOP2_NT64 : NM_COLOP2_NT32)                                                     \
+                 : (sizeof(T) == 8 ? NM_COLOP3_NT64 : NM_COLOP3_NT32))
 
 namespace nm {
 
@@ -893,21 +929,21 @@ __global__ __launch_bounds__(BLK) void k_colop(cx_t<T>* __restrict__ S, cx_t<T>*
     auto ld = [&](const V* base, int comp, V (&v)[R]) {
         const char* p = (const char*)(base + comp * cs);
 #pragma unroll
-        for (int m = 0; m < R; m++) v[m] = ld_nt<NM_NT(COLOP, T)>((const V*)(p + (lane + (uint32_t)m * mstep)));
+        for (int m = 0; m < R; m++) v[m] = ld_nt<NM_COLOP_OP_NT(OP, T)>((const V*)(p + (lane + (uint32_t)m * mstep)));
     };
     auto st = [&](V* base, int comp, const V (&v)[R]) {
         char* p = (char*)(base + comp * cs);
 #pragma unroll
-        for (int m = 0; m < R; m++) st_nt<NM_NT(COLOP, T)>((V*)(p + (lane + (uint32_t)m * mstep)), v[m]);
+        for (int m = 0; m < R; m++) st_nt<NM_COLOP_OP_NT(OP, T)>((V*)(p + (lane + (uint32_t)m * mstep)), v[m]);
     };
 #else
     auto ld = [&](const V* col, int comp, V (&v)[R]) {
 #pragma unroll
-        for (int m = 0; m < R; m++) v[m] = ld_nt<NM_NT(COLOP, T)>(col + comp * cs + (long)(t + m * G) * step);
+        for (int m = 0; m < R; m++) v[m] = ld_nt<NM_COLOP_OP_NT(OP, T)>(col + comp * cs + (long)(t + m * G) * step);
     };
     auto st = [&](V* col, int comp, const V (&v)[R]) {
 #pragma unroll
-        for (int m = 0; m < R; m++) st_nt<NM_NT(COLOP, T)>(col + comp * cs + (long)(t + m * G) * step, v[m]);
+        for (int m = 0; m < R; m++) st_nt<NM_COLOP_OP_NT(OP, T)>(col + comp * cs + (long)(t + m * G) * step, v[m]);
     };
 #endif
     // v <- D v along the column (forward FFT, i xi / n, inverse FFT)
