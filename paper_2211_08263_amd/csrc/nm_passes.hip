@@ -30,13 +30,14 @@
 #ifndef NM_STRESS_PF64
 #define NM_STRESS_PF64 2
 #endif
-// The stress pass keeps its twiddles in registers across its twelve transforms (measured:
-// 6% faster in FP64, 5% slower in FP32, where the registers cost occupancy).
+// The stress pass keeps its twiddles in registers across its twelve transforms (measured at
+// 256^3: 6% faster in FP64; in FP32, 132 -> 136 VGPRs at the same occupancy, 1-2% faster with
+// the streaming accesses below, 5% slower before them).
 #ifndef NM_STRESS_TWREG64
 #define NM_STRESS_TWREG64 1
 #endif
 #ifndef NM_STRESS_TWREG32
-#define NM_STRESS_TWREG32 0
+#define NM_STRESS_TWREG32 1
 #endif
 // Column passes address their tiles as a uniform base plus 32-bit lane offsets.
 #ifndef NM_COL_OFF32
