@@ -252,9 +252,10 @@ __global__ __launch_bounds__(kBlock) void k_xfwd(XFwdArgs a, const cx_t<T>* __re
 #pragma unroll
             for (int m = 0; m < R; m++) {
                 const int i = t + m * G;
-                const V uo = u[i], vo = vv[i], ao = aa[i];
+                const V uo = ld_nt<NM_NT(XFWD, T)>(u + i), vo = ld_nt<NM_NT(XFWD, T)>(vv + i),
+                        ao = ld_nt<NM_NT(XFWD, T)>(aa + i);
                 const V un = V{uo.x + dt * vo.x + h2 * ao.x, uo.y + dt * vo.y + h2 * ao.y};
-                u[i] = un;
+                st_nt<NM_NT(XFWD, T)>(u + i, un);
                 v[m] = un;
             }
         } else {
@@ -331,8 +332,8 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
 #pragma unroll
         for (int m = 0; m < R; m++) {
             const int n = t + m * G;
-            au[m] = ld_ok ? vp[n] : V{0, 0};
-            ao[m] = ld_ok ? ap[n] : V{0, 0};
+            au[m] = ld_ok ? ld_nt<NM_NT(XINV, T)>(vp + n) : V{0, 0};
+            ao[m] = ld_ok ? ld_nt<NM_NT(XINV, T)>(ap + n) : V{0, 0};
             ph[m] = ld_ok ? ((const uint32_t*)a.phase)[vline * M + n] : 0u;
             mk[m] = 0;
         }
@@ -382,8 +383,8 @@ __global__ __launch_bounds__(kBlock) void k_xinv(XInvArgs a, const cx_t<T>* __re
                     vn = V{0, 0};
                     an = V{0, 0};
                 }
-                vp[n] = vn;
-                ap[n] = an;
+                st_nt<NM_NT(XINV, T)>(vp + n, vn);
+                st_nt<NM_NT(XINV, T)>(ap + n, an);
             }
         } else {
             const bool zero_comp = (a.dim == 2) && ((line / a.lines_per_comp) % 3 == 2);
