@@ -48,11 +48,11 @@ OPERATOR_PASS_ID_BYTES = {"x_stress": 2, "x_inv_inertia": 2}
 # (profiles/hbm_traffic_256cube.md): FETCH_SIZE x 2.000 and WRITE_SIZE x 1.000, the factors a
 # 512 MiB device copy reads for those counters.  Valid only for the kernel sources they were
 # taken on (hash below); otherwise the traffic is reported as null.
-PMC_TRAFFIC = {("x_stress", "fp64"): {"fetch_kib": 410159.1, "write_kib": 786439.1},
-               ("x_stress", "fp32"): {"fetch_kib": 213318.9, "write_kib": 393217.0}}
+PMC_TRAFFIC = {("x_stress", "fp64"): {"fetch_kib": 410158.5, "write_kib": 786436.8},
+               ("x_stress", "fp32"): {"fetch_kib": 213319.0, "write_kib": 393216.5}}
 PMC_N = 256
 PMC_SCALE = {"fetch": 2.000, "write": 1.000}
-PMC_SOURCES_SHA16 = "e65838e94eed469e"
+PMC_SOURCES_SHA16 = "91438576f595bf0e"
 PMC_SOURCES = ("nm_common.h", "nm_fft.h", "nm_passes.h", "nm_passes.hip")
 
 
